@@ -1,0 +1,206 @@
+"""Benchmark of the SpGEMM hot path on one MI355X.
+
+Headline step: one two-phase product C = A*A (symbolic + numeric, FP64
+plus-times) of an R-MAT G500 matrix of scale 16, edge factor 16
+(duplicates summed, random symmetric permutation), inputs resident in HBM.
+value = 2 * flops / step time (flops = scalar multiplications).
+
+The JSON line also carries the roofline of the dominant kernel (algorithmic
+bytes per launch over its average launch time, HIP events on the plan's
+stream), the oracle timed on the host cores, and secondary modes.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpGEMM GFLOP/s (2·mults/s) + HBM GB/s, R-MAT A·A; learned/batched vs plain"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
+    return ap.parse_args()
+
+
+def value_width(sr):
+    return 1 if sr == "bool" else 8
+
+
+def kernel_bytes(name: str, st: dict, sr: str) -> float:
+    """Algorithmic bytes one launch of `name` moves (per-row byte model).
+
+    numeric rows R:  16|R| + annz(4+w) + 16 annz + flops(4+w) + cnnz(4+w)
+    symbolic rows R: 16|R| + 4 annz + 16 annz + 4 flops
+    (row extents of A and C, A entries, B row extents, B entries gathered,
+    C entries written; w = value bytes)."""
+    import paper_1510_00844_amd as spg
+    w = value_width(sr)
+    bins = {"tiny": [1], "small": [2], "dense": [12], "bitmap": [12]}
+    kind, _, tail = name.partition("_")
+    b = None
+    if tail.startswith("hash"):
+        T = int(tail[4:])
+        b = 3 + (T.bit_length() - 1 - 7)
+        idx = [b]
+    else:
+        idx = bins.get(tail)
+        if idx is None:
+            return float("nan")
+    if kind == "num":
+        R = sum(st["num_rows"][x] for x in idx)
+        an = sum(st["num_annz"][x] for x in idx)
+        f = sum(st["num_flops"][x] for x in idx)
+        cn = sum(st["num_cnnz"][x] for x in idx)
+        return 16.0 * R + an * (4 + w) + 16.0 * an + f * (4 + w) + cn * (4 + w)
+    if kind == "sym":
+        R = sum(st["sym_rows"][x] for x in idx)
+        an = sum(st["sym_annz"][x] for x in idx)
+        f = sum(st["sym_flops"][x] for x in idx)
+        return 16.0 * R + 4.0 * an + 16.0 * an + 4.0 * f
+    return float("nan")
+
+
+def model_bytes(m, annz, flops, cnnz, sr):
+    """One Gustavson numeric pass: 8(m+1) + nnzA(4+w) + 16 nnzA + flops(4+w)
+    + 8(m+1) + nnzC(4+w)."""
+    w = value_width(sr)
+    return 8.0 * (m + 1) * 2 + annz * (4 + w) + 16.0 * annz + flops * (4 + w) + cnnz * (4 + w)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(run with --gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1510_00844_amd as spg
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    A = synth.rmat(args.scale, 16, synth.G500, seed=2)
+    sr = "f64"
+    dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
+    plan = spg.Plan(profile=not args.no_profile)
+
+    def step():
+        rp, nnz = spg.spgemm_symbolic(plan, sr, dA, dA)
+        col, val = spg.spgemm_numeric(plan, sr, dA, dA, rp, nnz)
+        return nnz
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile_reset() if not args.no_profile else None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nnz = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    st = plan.stats()
+    flops = st["flops"]
+    gflops = 2.0 * flops / (ms * 1e-3) / 1e9
+    W = model_bytes(A.nrows, A.nnz, flops, nnz, sr)
+    prof = {} if args.no_profile else plan.profile_read()
+    kernels = {}
+    dom = None
+    for name, (launches, total) in prof.items():
+        per_step = total / args.steps
+        kernels[name] = {"launches_per_step": launches / args.steps, "ms_per_step": round(per_step, 4)}
+        if name in ("fill", "scan"):
+            continue
+        if dom is None or per_step > kernels[dom]["ms_per_step"]:
+            dom = name
+    roofline = None
+    if dom is not None:
+        launches, total = prof[dom]
+        avg_ms = total / launches
+        byts = kernel_bytes(dom, st, sr)
+        ach = byts / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": byts, "avg_launch_ms": round(avg_ms, 5)}
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "R-MAT G500 (.57,.19,.19,.05) scale %d edge factor 16, duplicates summed, "
+                               "symmetric permutation; C = A*A two-phase, plus-times FP64" % args.scale,
+                   "m": A.nrows, "nnz_a": A.nnz, "flops": flops, "nnz_c": nnz, "seed": 2},
+        "hbm_model_gbs": round(W / (ms * 1e-3) / 1e9, 2),
+        "hbm_model_frac": round(W / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_extras:
+        extras = {}
+        for xsr, kind in (("i64", "ones_i64"), ("bool", "true_bool")):
+            Ax = synth.with_values(A, kind)
+            dx = spg.DeviceCSR.from_arrays(Ax.nrows, Ax.ncols, Ax.row_ptr, Ax.col, Ax.val)
+            p2 = spg.Plan()
+            for _ in range(2):
+                rp, n2 = spg.spgemm_symbolic(p2, xsr, dx, dx)
+                spg.spgemm_numeric(p2, xsr, dx, dx, rp, n2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                rp, n2 = spg.spgemm_symbolic(p2, xsr, dx, dx)
+                spg.spgemm_numeric(p2, xsr, dx, dx, rp, n2)
+            torch.cuda.synchronize()
+            xms = (time.perf_counter() - t0) * 1e3 / reps
+            extras["c2_" + xsr] = {"ms_per_step": round(xms, 4),
+                                   "gflops": round(2.0 * flops / (xms * 1e-3) / 1e9, 3),
+                                   "hbm_model_gbs": round(model_bytes(A.nrows, A.nnz, flops, n2, xsr) / (xms * 1e-3) / 1e9, 2)}
+            p2.close()
+        out["modes"] = extras
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = os.cpu_count() or 1
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except Exception:
+            pass
+        t0 = time.perf_counter()
+        ref = oracle.spgemm(A, A, sr, nthreads=threads)
+        tc = time.perf_counter() - t0
+        assert ref.nnz == nnz
+        out["cpu_baseline"] = {"value": round(2.0 * flops / tc / 1e9, 4), "unit": "GFLOP/s", "cores": threads,
+                               "kind": "oracle", "seconds": round(tc, 3),
+                               "sample": "the whole C = A*A of this workload once (count pass + fill pass), "
+                                         "row-parallel OpenMP over %d threads" % threads}
+    plan.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * spgemm.h -- C ABI of the MI355X (gfx950) local sparse x sparse product and
+ * multiway layer merge: the per-process hot path of Split-3D-SpGEMM
+ * (Azad et al., "Exploiting Multiple Levels of Parallelism in Sparse
+ * Matrix-Matrix Multiplication", arXiv:1510.00844).
+ *
+ * Operation (Section 2 notation, Section 3 / Algorithm 1): C = A * B with
+ * A in S^{m x K}, B in S^{K x n} over a semiring S.  Only inner indices k in
+ * a window [k_lo, k_hi) take part, so one call computes one layer's partial
+ * product C_l = A(:,K_l) * B(K_l,:) of the split 3D distribution
+ * (Section 4, Algorithm 2, local multiply); the full product uses
+ * [0, K).  spgemm_merge_layers is LocalMerge (Section 4.3, Algorithm 2):
+ * the entry-wise semiring sum of c partial products.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are CSR, 0-based (the paper indexes from 1): int64 row
+ *     pointers (nrows+1 entries, row_ptr[0] == 0), int32 column indices
+ *     strictly increasing inside each row, and a value array of nnz
+ *     elements: double (SPG_SR_PLUS_TIMES_F64), int64_t
+ *     (SPG_SR_PLUS_TIMES_I64) or uint8_t 0/1 (SPG_SR_OR_AND_BOOL; val may
+ *     be NULL there, meaning every stored entry is true).
+ *   - All array pointers inside spg_csr and all output arrays are DEVICE
+ *     pointers on the plan's device, owned by the caller.  The library never
+ *     frees them.  Host pointers appear only where a parameter says "host".
+ *   - The stored set of C is structural: (i,j) is stored iff some k in the
+ *     window has A(i,k) and B(k,j) stored.  Explicit zeros and entries whose
+ *     value cancels to zero stay stored (Section 5 counts explicit zeros as
+ *     nonzeros).  Output rows are sorted by column (Section 5.1.1).
+ *   - INT64 arithmetic wraps modulo 2^64.  FP64 sums may be formed in any
+ *     order (within 1e-12 relative of an ascending-k sum for the workloads
+ *     here); structure, INT64 and boolean results are exact.
+ *   - Every call is asynchronous on the plan's stream except where a
+ *     parameter is a host output (those synchronize the stream).
+ *   - Errors are reported only through the return code; nothing aborts or
+ *     throws.  spg_last_error() gives a message for the calling thread.
+ *   - A plan is used by one host thread at a time.
+ */
+#ifndef SPGEMM_MI355X_H
+#define SPGEMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPG_OK = 0,
+    SPG_ERR_ARG = 1,           /* NULL pointer, bad window, bad enum, nlayers < 1 */
+    SPG_ERR_SHAPE = 2,         /* A.ncols != B.nrows, layer shapes differ */
+    SPG_ERR_NOT_CANONICAL = 3, /* validate option found unsorted/out-of-range input */
+    SPG_ERR_INDEX_RANGE = 4,   /* a dimension >= 2^31, or > 2^19 columns on a path that needs fewer */
+    SPG_ERR_OOM = 5,           /* device scratch allocation failed */
+    SPG_ERR_CAPACITY = 6,      /* a caller-provided capacity is too small */
+    SPG_ERR_HIP = 7,           /* a HIP runtime call failed; see spg_last_error() */
+    SPG_ERR_STATE = 8          /* numeric called without the matching symbolic call */
+} spg_status;
+
+typedef enum {
+    SPG_SR_PLUS_TIMES_F64 = 0,
+    SPG_SR_PLUS_TIMES_I64 = 1,
+    SPG_SR_OR_AND_BOOL = 2
+} spg_semiring;
+
+typedef struct {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nnz;
+    const int64_t* row_ptr; /* device, nrows+1 */
+    const int32_t* col;     /* device, nnz */
+    const void* val;        /* device, nnz; NULL allowed only for the boolean semiring */
+} spg_csr;
+
+/* Tuning options.  Zero fields take the defaults of spg_default_opts(). */
+typedef struct {
+    int32_t validate;          /* 1: check inputs are canonical CSR on the device first */
+    int32_t small_max_flops;   /* rows with at most this many products use one wave (<= 64) */
+    int32_t hash_max_flops;    /* symbolic: LDS hash table up to this many products per row */
+    int32_t hash_max_nnz;      /* numeric: LDS hash table up to this many outputs per row */
+    int32_t dense_chunk_cols;  /* numeric dense rows: columns per LDS chunk (power of two) */
+    int32_t profile;           /* 1: time every kernel launch with HIP events */
+    int32_t reserved[10];
+} spg_opts;
+
+typedef struct spg_plan_s* spg_plan;
+
+void spg_default_opts(spg_opts* opts);
+
+/* Create a plan bound to the current HIP device and to `stream` (a
+ * hipStream_t; NULL = the null stream).  The plan owns all scratch memory
+ * (row work counts, bin lists, split tables) and reuses it across calls. */
+spg_status spg_plan_create(spg_plan* plan, void* stream, const spg_opts* opts);
+spg_status spg_plan_destroy(spg_plan plan);
+spg_status spg_plan_set_stream(spg_plan plan, void* stream);
+
+/* Symbolic phase: per-row output counts of C = A(:,K) B(K,:), K = [k_lo,k_hi).
+ * c_row_ptr: device, m+1 entries, caller-owned; receives the exclusive
+ * prefix sum of the row counts (c_row_ptr[m] = nnz(C)).
+ * c_nnz: host; if not NULL it receives nnz(C) and the stream is synchronized.
+ * Errors: SPG_ERR_SHAPE if A.ncols != B.nrows; SPG_ERR_ARG unless
+ * 0 <= k_lo <= k_hi <= A.ncols. */
+spg_status spgemm_symbolic(spg_plan plan, spg_semiring sr, const spg_csr* A, const spg_csr* B,
+                           int64_t k_lo, int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz);
+
+/* Numeric phase: fills c_col (int32) and c_val (typed as the semiring) for the
+ * row pointers computed by the last spgemm_symbolic on this plan, which must
+ * have had the same A, B and window (SPG_ERR_STATE otherwise).  Rows come out
+ * sorted by column.  c_val may be NULL to produce the structure only. */
+spg_status spgemm_numeric(spg_plan plan, spg_semiring sr, const spg_csr* A, const spg_csr* B,
+                          int64_t k_lo, int64_t k_hi, const int64_t* c_row_ptr, int32_t* c_col,
+                          void* c_val);
+
+/* LocalMerge: out = sum over l of layers[l] (entry-wise, semiring add, equal
+ * (i,j) combined in ascending layer order).  `layers` is a HOST array of
+ * nlayers descriptors of device matrices, all nrows x ncols and canonical.
+ * Call twice: first with out_col == NULL (count pass: fills out_row_ptr,
+ * m+1 device entries, and *out_nnz on the host, synchronizing), then with
+ * out_col/out_val sized from *out_nnz (fill pass, same layers). */
+spg_status spgemm_merge_layers(spg_plan plan, spg_semiring sr, int32_t nlayers,
+                               const spg_csr* layers, int64_t* out_row_ptr, int32_t* out_col,
+                               void* out_val, int64_t* out_nnz);
+
+/* Row classes ("bins") the symbolic/numeric passes sort rows into. */
+enum {
+    SPG_BIN_EMPTY = 0,  /* no products */
+    SPG_BIN_TINY = 1,   /* one stored A entry in the window: output = scaled B row */
+    SPG_BIN_SMALL = 2,  /* few products: one wave, keys in registers */
+    SPG_BIN_HASH0 = 3,  /* LDS hash table bins, 128 << (b - SPG_BIN_HASH0) slots */
+    SPG_BIN_DENSE = 12, /* large rows: LDS bitmap / dense chunked accumulator */
+    SPG_NBINS = 13
+};
+
+/* Statistics of the last symbolic (and numeric) call, read back on demand
+ * (synchronizes).  Per bin: rows, products (flops) and A entries; for the
+ * numeric pass also output entries. */
+typedef struct {
+    int64_t m, n, k;
+    int64_t flops;      /* total scalar multiplications */
+    int64_t nnz_c;
+    int64_t sym_rows[SPG_NBINS], sym_flops[SPG_NBINS], sym_annz[SPG_NBINS];
+    int64_t num_rows[SPG_NBINS], num_flops[SPG_NBINS], num_annz[SPG_NBINS], num_cnnz[SPG_NBINS];
+    int32_t dense_chunk_cols;
+    int32_t dense_chunks;
+} spg_stats;
+spg_status spg_plan_stats(spg_plan plan, spg_stats* out);
+
+/* Kernel timing (opts.profile = 1): events recorded on the plan's stream
+ * around every launch.  Fills up to cap records of (name, launches, total
+ * milliseconds) accumulated since the last reset; returns the count in *n. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} spg_kernel_time;
+spg_status spg_profile_read(spg_plan plan, spg_kernel_time* out, int32_t cap, int32_t* n);
+spg_status spg_profile_reset(spg_plan plan);
+
+const char* spg_status_string(spg_status s);
+const char* spg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,247 @@
+"""Python binding of the MI355X SpGEMM library (libspgemm.so).
+
+Argument marshalling only: every step of the product and the merge runs in
+the HIP kernels behind the C ABI of include/spgemm.h.  torch tensors own the
+device buffers and supply the stream; no torch operation takes part in the
+computation.  If the library is not built this module raises on first use;
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspgemm.so")
+
+SEMIRINGS = {"f64": 0, "i64": 1, "bool": 2}
+TORCH_DTYPE = {"f64": torch.float64, "i64": torch.int64, "bool": torch.uint8}
+
+NBINS = 13
+BIN_NAMES = ["empty", "tiny", "small"] + ["hash%d" % (128 << b) for b in range(9)] + ["dense"]
+
+
+class SpgError(RuntimeError):
+    def __init__(self, status: int, name: str, msg: str):
+        super().__init__("%s: %s" % (name, msg))
+        self.status = status
+        self.name = name
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("validate", ctypes.c_int32), ("small_max_flops", ctypes.c_int32),
+                ("hash_max_flops", ctypes.c_int32), ("hash_max_nnz", ctypes.c_int32),
+                ("dense_chunk_cols", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 10)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("flops", ctypes.c_int64), ("nnz_c", ctypes.c_int64),
+                ("sym_rows", ctypes.c_int64 * NBINS), ("sym_flops", ctypes.c_int64 * NBINS),
+                ("sym_annz", ctypes.c_int64 * NBINS),
+                ("num_rows", ctypes.c_int64 * NBINS), ("num_flops", ctypes.c_int64 * NBINS),
+                ("num_annz", ctypes.c_int64 * NBINS), ("num_cnnz", ctypes.c_int64 * NBINS),
+                ("dense_chunk_cols", ctypes.c_int32), ("dense_chunks", ctypes.c_int32)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libspgemm.so (built in-tree by build.py); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libspgemm.so is not built (run __graft_entry__.build() or "
+                               "python paper_1510_00844_amd/build.py); no fallback exists")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        CP = ctypes.POINTER(_Csr)
+        sig = {
+            "spg_default_opts": ([ctypes.POINTER(Opts)], None),
+            "spg_plan_create": ([ctypes.POINTER(P), P, ctypes.POINTER(Opts)], ctypes.c_int),
+            "spg_plan_destroy": ([P], ctypes.c_int),
+            "spg_plan_set_stream": ([P, P], ctypes.c_int),
+            "spgemm_symbolic": ([P, ctypes.c_int, CP, CP, I64, I64, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "spgemm_numeric": ([P, ctypes.c_int, CP, CP, I64, I64, P, P, P], ctypes.c_int),
+            "spgemm_merge_layers": ([P, ctypes.c_int, I32, CP, P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "spg_plan_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
+            "spg_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], ctypes.c_int),
+            "spg_profile_reset": ([P], ctypes.c_int),
+            "spg_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "spg_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        L = lib()
+        raise SpgError(status, L.spg_status_string(status).decode(), L.spg_last_error().decode())
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix in device memory: int64 row_ptr, int32 col, typed val."""
+
+    nrows: int
+    ncols: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: Optional[torch.Tensor]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_arrays(nrows, ncols, row_ptr, col, val, device="cuda") -> "DeviceCSR":
+        rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(device).contiguous()
+        c = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
+        v = None if val is None else torch.as_tensor(val).to(device).contiguous()
+        return DeviceCSR(int(nrows), int(ncols), rp, c, v)
+
+    def to_numpy(self):
+        return (self.row_ptr.cpu().numpy(), self.col.cpu().numpy(),
+                None if self.val is None else self.val.cpu().numpy())
+
+    def _c(self, sr: Optional[str] = None) -> _Csr:
+        if self.val is not None and sr is not None:
+            want = TORCH_DTYPE[sr]
+            if self.val.dtype != want:
+                raise TypeError("values are %s, semiring %s needs %s" % (self.val.dtype, sr, want))
+        return _Csr(self.nrows, self.ncols, self.nnz, self.row_ptr.data_ptr(),
+                    self.col.data_ptr() if self.nnz else None,
+                    None if self.val is None or self.nnz == 0 else self.val.data_ptr())
+
+
+class Plan:
+    """Owns an spg_plan bound to a device and a stream (default: torch's
+    current stream on that device)."""
+
+    def __init__(self, device=None, stream: Optional[torch.cuda.Stream] = None, validate=False,
+                 profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
+                 dense_chunk_cols=0):
+        L = lib()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            o = Opts()
+            L.spg_default_opts(ctypes.byref(o))
+            o.validate = int(validate)
+            o.profile = int(profile)
+            for name, v in (("small_max_flops", small_max_flops), ("hash_max_flops", hash_max_flops),
+                            ("hash_max_nnz", hash_max_nnz), ("dense_chunk_cols", dense_chunk_cols)):
+                if v:
+                    setattr(o, name, int(v))
+            h = ctypes.c_void_p()
+            _check(L.spg_plan_create(ctypes.byref(h), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(o)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().spg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().spg_plan_stats(self.handle, ctypes.byref(s)))
+        d = {k: getattr(s, k) for k in ("m", "n", "k", "flops", "nnz_c", "dense_chunk_cols", "dense_chunks")}
+        for k in ("sym_rows", "sym_flops", "sym_annz", "num_rows", "num_flops", "num_annz", "num_cnnz"):
+            d[k] = list(getattr(s, k))
+        return d
+
+    def profile_read(self) -> dict:
+        arr = (KernelTime * 64)()
+        n = ctypes.c_int32()
+        _check(lib().spg_profile_read(self.handle, arr, 64, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 64))}
+
+    def profile_reset(self):
+        _check(lib().spg_profile_reset(self.handle))
+
+
+def _window(A: DeviceCSR, k_lo, k_hi):
+    return (0 if k_lo is None else int(k_lo)), (A.ncols if k_hi is None else int(k_hi))
+
+
+def spgemm_symbolic(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, k_lo=None, k_hi=None,
+                    c_row_ptr: Optional[torch.Tensor] = None, want_nnz: bool = True):
+    """Row pointers of C = A(:,K) B(K,:) (device tensor, m+1) and nnz(C)."""
+    k_lo, k_hi = _window(A, k_lo, k_hi)
+    if c_row_ptr is None:
+        c_row_ptr = torch.empty(A.nrows + 1, dtype=torch.int64, device=plan.device)
+    nnz = ctypes.c_int64(-1)
+    a, b = A._c(), B._c()
+    _check(lib().spgemm_symbolic(plan.handle, SEMIRINGS[sr], ctypes.byref(a), ctypes.byref(b), k_lo, k_hi,
+                                 ctypes.c_void_p(c_row_ptr.data_ptr()),
+                                 ctypes.byref(nnz) if want_nnz else None))
+    return c_row_ptr, (nnz.value if want_nnz else None)
+
+
+def spgemm_numeric(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, c_row_ptr: torch.Tensor, nnz: int,
+                   k_lo=None, k_hi=None, values: bool = True, c_col=None, c_val=None):
+    """Column indices and values of C for the row pointers of the matching
+    symbolic call."""
+    k_lo, k_hi = _window(A, k_lo, k_hi)
+    if c_col is None:
+        c_col = torch.empty(max(nnz, 0), dtype=torch.int32, device=plan.device)
+    if values and c_val is None:
+        c_val = torch.empty(max(nnz, 0), dtype=TORCH_DTYPE[sr], device=plan.device)
+    a, b = A._c(sr), B._c(sr)
+    _check(lib().spgemm_numeric(plan.handle, SEMIRINGS[sr], ctypes.byref(a), ctypes.byref(b), k_lo, k_hi,
+                                ctypes.c_void_p(c_row_ptr.data_ptr()),
+                                ctypes.c_void_p(c_col.data_ptr()) if nnz > 0 else None,
+                                ctypes.c_void_p(c_val.data_ptr()) if (values and nnz > 0) else None))
+    return c_col, (c_val if values else None)
+
+
+def spgemm(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, k_lo=None, k_hi=None, values=True) -> DeviceCSR:
+    """Two-phase product C = A(:,K) B(K,:) as a DeviceCSR."""
+    rp, nnz = spgemm_symbolic(plan, sr, A, B, k_lo, k_hi)
+    col, val = spgemm_numeric(plan, sr, A, B, rp, nnz, k_lo, k_hi, values=values)
+    return DeviceCSR(A.nrows, B.ncols, rp, col, val)
+
+
+def spgemm_merge_layers(plan: Plan, sr: str, layers: Sequence[DeviceCSR], values=True) -> DeviceCSR:
+    """LocalMerge: entry-wise semiring sum of the layers (count + fill pass)."""
+    c = len(layers)
+    arr = (_Csr * c)(*[L._c(sr if values else None) for L in layers])
+    m, n = layers[0].nrows, layers[0].ncols
+    rp = torch.empty(m + 1, dtype=torch.int64, device=plan.device)
+    nnz = ctypes.c_int64(-1)
+    _check(lib().spgemm_merge_layers(plan.handle, SEMIRINGS[sr], c, arr, ctypes.c_void_p(rp.data_ptr()),
+                                     None, None, ctypes.byref(nnz)))
+    col = torch.empty(max(nnz.value, 0), dtype=torch.int32, device=plan.device)
+    val = torch.empty(max(nnz.value, 0), dtype=TORCH_DTYPE[sr], device=plan.device) if values else None
+    if nnz.value > 0:
+        _check(lib().spgemm_merge_layers(plan.handle, SEMIRINGS[sr], c, arr, ctypes.c_void_p(rp.data_ptr()),
+                                         ctypes.c_void_p(col.data_ptr()),
+                                         ctypes.c_void_p(val.data_ptr()) if values else None, None))
+    return DeviceCSR(m, n, rp, col, val)

@@ -1,0 +1,270 @@
+// Numeric phase: C(i,j) = (+)-sum over stored A(i,k), k in window, of
+// A(i,k) (x) B(k,j), written as canonical CSR rows sorted by column
+// (Section 5.1.1) at the offsets the symbolic phase produced.  Bins:
+//   TINY   one A entry: C(i,:) = a (x) B(k,:), already sorted (no accumulator)
+//   SMALL  <= 64 products: one wave per row; products sorted across the wave
+//          by (column, product order), equal columns folded left to right,
+//          which is ascending k (the order of Algorithm 1)
+//   HASH   workgroup per row: LDS open-addressing table sized >= 2 slots per
+//          output, semiring add by LDS atomics, then compaction and an LDS
+//          bitonic sort by column
+//   DENSE  workgroup per row sweeping column chunks of W: an LDS dense
+//          accumulator plus occupancy bitmap per chunk (the sparse
+//          accumulator of Section 3, blocked by columns so it fits LDS);
+//          the bitmap scan emits columns in order, so no sort is needed.
+#pragma once
+#include "products.hpp"
+#include "symbolic.hpp"
+
+namespace spg {
+
+// One wave per row, rows given by a list.
+template <int SR>
+__global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* rows, int32_t nrows,
+                                                  const int64_t* a_beg, const int64_t* c_rp,
+                                                  int32_t* c_col, void* c_val) {
+    typedef Sr<SR> S;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    const int64_t i = rows[r];
+    const int64_t p = a_beg[i];
+    const int64_t k = A.col[p];
+    const typename S::acc_t a = S::load(A.val, p);
+    const int64_t bs = B.rp[k], be = B.rp[k + 1];
+    const int64_t off = c_rp[i] - bs;
+    for (int64_t q = bs + lane_id(); q < be; q += SPG_WAVE) {
+        c_col[off + q] = B.col[q];
+        if (c_val) S::store(c_val, off + q, S::mul(a, S::load(B.val, q)));
+    }
+}
+
+template <int SR>
+__global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
+                                                   const int64_t* a_beg, const int64_t* a_end,
+                                                   const int64_t* c_rp, int32_t* c_col, void* c_val) {
+    typedef Sr<SR> S;
+    typedef typename S::acc_t V;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    const int64_t i = rows[r];
+    const int lane = lane_id();
+    int64_t p = 0, q = 0;
+    bool have = wave_locate_product(A, B, a_beg[i], a_end[i], p, q);
+    V v = S::zero();
+    uint64_t key = ~0ull;
+    if (have) {
+        v = S::mul(S::load(A.val, p), S::load(B.val, q));
+        key = ((uint64_t)(uint32_t)B.col[q] << 6) | (uint64_t)lane;  // (column, product order)
+    }
+    key = wave_bitonic_sort_u64(key);
+    const bool valid = key != ~0ull;
+    v = __shfl(v, (int)(key & 63), SPG_WAVE);  // value travels with its key
+    const uint64_t col = key >> 6;
+    const uint64_t prev = __shfl_up(col, 1, SPG_WAVE);
+    const bool head = valid && (lane == 0 || prev != col);
+    // fold the run that starts at each head, left to right
+    V acc = v;
+    bool open = head;
+    for (int s = 1; s < SPG_WAVE; ++s) {
+        if (!__any(open)) break;
+        uint64_t ncol = __shfl_down(col, s, SPG_WAVE);
+        V nv = __shfl_down(v, s, SPG_WAVE);
+        bool nvalid = __shfl_down((int)valid, s, SPG_WAVE) != 0;
+        open = open && (lane + s < SPG_WAVE) && nvalid && ncol == col;
+        if (open) acc = S::add(acc, nv);
+    }
+    const uint64_t heads = __ballot(head);
+    if (head) {
+        const int64_t o = c_rp[i] + lanes_below(heads);
+        c_col[o] = (int32_t)col;
+        if (c_val) S::store(c_val, o, acc);
+    }
+}
+
+template <int SR, int NT, int LOG2T>
+__global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* rows,
+                                                 const int64_t* a_beg, const int64_t* a_end,
+                                                 const int64_t* c_rp, int32_t* c_col, void* c_val) {
+    typedef Sr<SR> S;
+    typedef typename S::acc_t V;
+    constexpr int T = 1 << LOG2T;
+    constexpr int PER = T / NT;  // table slots owned by a thread during compaction
+    static_assert(PER >= 1, "table smaller than block");
+    __shared__ int32_t tkey[T];
+    __shared__ V tval[T];
+    __shared__ ProductLds<NT> L;
+    __shared__ int32_t red[NT / SPG_WAVE + 1];
+    const int64_t i = rows[blockIdx.x];
+    for (int t = threadIdx.x; t < T; t += NT) {
+        tkey[t] = EMPTY_KEY;
+        tval[t] = S::zero();
+    }
+    __syncthreads();
+    for_each_product<NT>(
+        a_beg[i], a_end[i], L,
+        [&](int64_t p, int64_t& bs, int32_t& len) {
+            int64_t k = A.col[p];
+            bs = B.rp[k];
+            len = (int32_t)(B.rp[k + 1] - bs);
+        },
+        [&](int, int64_t) {},
+        [&](int, int64_t p, int64_t q) {
+            const int32_t j = B.col[q];
+            const V v = S::mul(S::load(A.val, p), S::load(B.val, q));
+            uint32_t h = hash_slot(j, LOG2T);
+            // the table has >= 2 slots per output of the symbolic count, so a
+            // probe ends within T steps; the cap only guards inputs that
+            // changed between the two phases
+            for (int probes = 0; probes < T; ++probes) {
+                int32_t cur = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cur == EMPTY_KEY) {
+                    int32_t old = atomicCAS(&tkey[h], EMPTY_KEY, j);
+                    cur = old == EMPTY_KEY ? j : old;
+                }
+                if (cur == j) {
+                    S::lds_add(&tval[h], v);
+                    break;
+                }
+                h = (h + 1) & (T - 1);
+            }
+        });
+    // compaction: slots [t*PER, (t+1)*PER) -> registers
+    int32_t rk[PER];
+    V rv[PER];
+    int32_t mine = 0;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        rk[s] = tkey[threadIdx.x * PER + s];
+        rv[s] = tval[threadIdx.x * PER + s];
+        mine += rk[s] != EMPTY_KEY;
+    }
+    __syncthreads();  // every slot is in registers before the table is reused
+    int32_t cnt;
+    int32_t pos = block_exclusive_scan<NT, int32_t>(mine, &cnt, red);
+    const int64_t o = c_rp[i];
+    const int32_t cnt_sym = (int32_t)(c_rp[i + 1] - o);
+    if (cnt > T / 2) cnt = T / 2;  // sort buffer capacity; only reached if inputs changed
+    // reuse the table: compacted values in tkey's bytes, sort keys in tval's
+    V* cval = reinterpret_cast<V*>(tkey);
+    uint64_t* skey = reinterpret_cast<uint64_t*>(tval);
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        if (rk[s] != EMPTY_KEY && pos < cnt) {
+            cval[pos] = rv[s];
+            skey[pos] = ((uint64_t)(uint32_t)rk[s] << 32) | (uint64_t)pos;
+            ++pos;
+        }
+    }
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int t = cnt + threadIdx.x; t < P; t += NT) skey[t] = ~0ull;
+    __syncthreads();
+    block_bitonic_sort_u64<NT>(skey, P);
+    const int32_t nout = cnt < cnt_sym ? cnt : cnt_sym;
+    for (int t = threadIdx.x; t < nout; t += NT) {
+        uint64_t kk = skey[t];
+        c_col[o + t] = (int32_t)(kk >> 32);
+        if (c_val) S::store(c_val, o + t, cval[kk & 0xffffffffu]);
+    }
+}
+
+// Column split table for the dense sweep: split[k*(P+1)+c] = offset inside
+// B(k,:) of the first entry with column >= c*W (c = 0..P).
+__global__ void __launch_bounds__(256) k_split_table(Csr B, int32_t W, int32_t P, int32_t* split) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = B.nrows * (int64_t)(P + 1);
+    if (idx >= total) return;
+    const int64_t k = idx / (P + 1);
+    const int c = (int)(idx - k * (P + 1));
+    const int64_t rs = B.rp[k], re = B.rp[k + 1];
+    int64_t r;
+    if (c == 0) r = rs;
+    else if (c == P) r = re;
+    else r = lower_bound_col(B.col, rs, re, (int64_t)c * W);
+    split[idx] = (int32_t)(r - rs);
+}
+
+template <int SR, int NT, int W>
+__global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* rows,
+                                                  const int64_t* a_beg, const int64_t* a_end,
+                                                  const int32_t* split, int32_t P,
+                                                  const int64_t* c_rp, int32_t* c_col, void* c_val) {
+    typedef Sr<SR> S;
+    typedef typename S::acc_t V;
+    constexpr int NWD = W / 32;
+    __shared__ V acc[W];
+    __shared__ uint32_t bits[NWD];
+    __shared__ int32_t wpre[NWD];
+    __shared__ V s_av[NT];
+    __shared__ ProductLds<NT> L;
+    __shared__ int32_t red[NT / SPG_WAVE + 1];
+    const int64_t i = rows[blockIdx.x];
+    const int64_t beg = a_beg[i], end = a_end[i];
+    int64_t off = c_rp[i];
+    const int64_t row_end = c_rp[i + 1];
+    for (int c = 0; c < P; ++c) {
+        for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
+        for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
+        __syncthreads();
+        const int32_t cbase = c * W;
+        for_each_product<NT>(
+            beg, end, L,
+            [&](int64_t p, int64_t& bs, int32_t& len) {
+                int64_t k = A.col[p];
+                int64_t rs = B.rp[k];
+                if (P > 1) {
+                    const int32_t* sp = split + k * (P + 1) + c;
+                    bs = rs + sp[0];
+                    len = sp[1] - sp[0];
+                } else {
+                    bs = rs;
+                    len = (int32_t)(B.rp[k + 1] - rs);
+                }
+            },
+            [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
+            [&](int t, int64_t, int64_t q) {
+                const int32_t j = B.col[q] - cbase;
+                S::lds_add(&acc[j], S::mul(s_av[t], S::load(B.val, q)));
+                atomicOr(&bits[j >> 5], 1u << (j & 31));
+            });
+        // exclusive prefix of per-word popcounts
+        int32_t chunk_total = 0;
+        {
+            // NWD <= 4*NT: each thread sums up to 4 consecutive words
+            constexpr int WPT = (NWD + NT - 1) / NT;
+            int32_t wc[WPT];
+            int32_t s = 0;
+#pragma unroll
+            for (int x = 0; x < WPT; ++x) {
+                int w = threadIdx.x * WPT + x;
+                wc[x] = w < NWD ? __popc(bits[w]) : 0;
+                s += wc[x];
+            }
+            int32_t pre = block_exclusive_scan<NT, int32_t>(s, &chunk_total, red);
+#pragma unroll
+            for (int x = 0; x < WPT; ++x) {
+                int w = threadIdx.x * WPT + x;
+                if (w < NWD) wpre[w] = pre;
+                pre += wc[x];
+            }
+        }
+        __syncthreads();
+        if (chunk_total) {
+            for (int j = threadIdx.x; j < W; j += NT) {
+                const uint32_t wbits = bits[j >> 5];
+                const uint32_t b = 1u << (j & 31);
+                if (wbits & b) {
+                    const int64_t o = off + wpre[j >> 5] + __popc(wbits & (b - 1));
+                    if (o < row_end) {
+                        c_col[o] = cbase + j;
+                        if (c_val) S::store(c_val, o, acc[j]);
+                    }
+                }
+            }
+        }
+        off += chunk_total;
+        __syncthreads();
+    }
+}
+
+}  // namespace spg

@@ -1,0 +1,280 @@
+// Row analysis and binning (the work estimate of Section 2: flops(A,B)
+// counts scalar multiplications; Gustavson's cost is O(flops + nnz + m + n),
+// Section 3).  For each row i of A, restricted to the inner window
+// [k_lo, k_hi):
+//   a_beg[i], a_end[i]  index range of A's stored entries inside the window
+//   flops[i]            sum over those entries k of nnz(B(k,:))
+//   maxb[i]             max over those k of nnz(B(k,:))  (a lower bound of nnz(C(i,:)))
+//   bin[i]              the accumulator class the row is sent to
+// Rows with at most LONG_ROW entries are handled by 16-lane groups; longer
+// rows are queued for a workgroup each so no wave walks a hub row alone.
+#pragma once
+#include "common.hpp"
+
+namespace spg {
+
+struct BinParams {
+    int32_t small_max_flops;  // <= 64
+    int32_t hash_max_flops;   // symbolic hash limit
+    int32_t hash_max_nnz;     // numeric hash limit
+    int32_t dense_ok;         // symbolic LDS bitmap allowed (n <= 2^19)
+    int64_t ncols;            // n
+};
+
+constexpr int NBINS = 13;
+constexpr int BIN_EMPTY = 0, BIN_TINY = 1, BIN_SMALL = 2, BIN_HASH0 = 3, BIN_DENSE = 12;
+constexpr int LONG_ROW = 512;
+constexpr int HASH_MIN_LOG2 = 7;  // 128 slots
+
+__device__ inline int ceil_log2_i64(int64_t x) {
+    return x <= 1 ? 0 : 64 - __clzll((unsigned long long)(x - 1));
+}
+
+// Symbolic bin from the row's work.
+__device__ inline int sym_bin(int64_t flops, int64_t annz, const BinParams& bp) {
+    if (flops == 0) return BIN_EMPTY;
+    if (annz == 1) return BIN_TINY;
+    if (flops <= bp.small_max_flops) return BIN_SMALL;
+    // a bitmap over all n columns costs n/32 words to clear and count; use it
+    // once the row's products outnumber that, or once a hash table would not fit
+    bool bitmap_cheaper = bp.dense_ok && flops * 32 >= bp.ncols;
+    if (flops <= bp.hash_max_flops && !bitmap_cheaper) {
+        int lg = ceil_log2_i64(2 * flops);
+        if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
+        return BIN_HASH0 + (lg - HASH_MIN_LOG2);
+    }
+    return BIN_DENSE;
+}
+
+// Numeric bin from the exact output count.
+__device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, const BinParams& bp) {
+    if (cnt == 0) return BIN_EMPTY;
+    if (annz == 1) return BIN_TINY;
+    if (flops <= bp.small_max_flops) return BIN_SMALL;
+    if (cnt <= bp.hash_max_nnz) {
+        int lg = ceil_log2_i64(2 * cnt);
+        if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
+        return BIN_HASH0 + (lg - HASH_MIN_LOG2);
+    }
+    return BIN_DENSE;
+}
+
+struct RowInfoOut {
+    int64_t* a_beg;
+    int64_t* a_end;
+    int64_t* flops;
+    int32_t* maxb;
+    uint8_t* bin;
+    int64_t* cnt;        // symbolic counts (c_row_ptr + 1); EMPTY/TINY rows written here
+    int64_t* bin_stats;  // [3][NBINS]: rows, flops, A entries
+    int32_t* long_rows;  // queue of rows with more than LONG_ROW entries
+    int32_t* long_count;
+};
+
+__device__ inline int64_t lower_bound_col(const int32_t* col, int64_t lo, int64_t hi, int64_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)col[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline void finish_row(int64_t i, int64_t beg, int64_t end, int64_t f, int32_t mb,
+                                  const BinParams& bp, const RowInfoOut& o, int* s_hist,
+                                  int64_t* s_flops, int64_t* s_annz) {
+    o.a_beg[i] = beg;
+    o.a_end[i] = end;
+    o.flops[i] = f;
+    o.maxb[i] = mb;
+    int b = sym_bin(f, end - beg, bp);
+    o.bin[i] = (uint8_t)b;
+    if (b == BIN_EMPTY) o.cnt[i] = 0;
+    else if (b == BIN_TINY) o.cnt[i] = f;  // nnz(C(i,:)) = nnz(B(k,:)) exactly
+    atomicAdd(&s_hist[b], 1);
+    atomicAdd((unsigned long long*)&s_flops[b], (unsigned long long)f);
+    atomicAdd((unsigned long long*)&s_annz[b], (unsigned long long)(end - beg));
+}
+
+__device__ inline void flush_stats(const RowInfoOut& o, int* s_hist, int64_t* s_flops,
+                                   int64_t* s_annz) {
+    if (threadIdx.x < NBINS) {
+        int b = threadIdx.x;
+        if (s_hist[b]) {
+            atomicAdd((unsigned long long*)&o.bin_stats[b], (unsigned long long)s_hist[b]);
+            atomicAdd((unsigned long long*)&o.bin_stats[NBINS + b], (unsigned long long)s_flops[b]);
+            atomicAdd((unsigned long long*)&o.bin_stats[2 * NBINS + b], (unsigned long long)s_annz[b]);
+        }
+    }
+}
+
+// 256 threads = 16 groups of 16 lanes, one row per group.
+__global__ void __launch_bounds__(256) k_rowinfo(Csr A, Csr B, int64_t k_lo, int64_t k_hi,
+                                                 int full_window, BinParams bp, RowInfoOut o) {
+    __shared__ int s_hist[NBINS];
+    __shared__ int64_t s_flops[NBINS], s_annz[NBINS];
+    if (threadIdx.x < NBINS) {
+        s_hist[threadIdx.x] = 0;
+        s_flops[threadIdx.x] = 0;
+        s_annz[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
+    const int64_t i = (int64_t)blockIdx.x * 16 + g;
+    bool active = i < A.nrows;
+    int64_t beg = 0, end = 0;
+    if (active) {
+        beg = A.rp[i];
+        end = A.rp[i + 1];
+        if (!full_window) {
+            // the A row is sorted by column: binary search the window edges
+            beg = lower_bound_col(A.col, beg, end, k_lo);
+            end = lower_bound_col(A.col, beg, end, k_hi);
+        }
+        if (end - beg > LONG_ROW) {
+            if (gl == 0) {
+                int slot = atomicAdd(o.long_count, 1);
+                o.long_rows[slot] = (int32_t)i;
+            }
+            active = false;
+        }
+    }
+    int64_t f = 0;
+    int32_t mb = 0;
+    if (active) {
+        for (int64_t p = beg + gl; p < end; p += 16) {
+            int64_t k = A.col[p];
+            int64_t len = B.rp[k + 1] - B.rp[k];
+            f += len;
+            mb = len > mb ? (int32_t)len : mb;
+        }
+    }
+    // reduce inside the 16-lane group (xor offsets < 16 stay in the group)
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1) {
+        f += __shfl_xor(f, d, SPG_WAVE);
+        int32_t o2 = __shfl_xor(mb, d, SPG_WAVE);
+        mb = o2 > mb ? o2 : mb;
+    }
+    if (active && gl == 0) finish_row(i, beg, end, f, mb, bp, o, s_hist, s_flops, s_annz);
+    __syncthreads();
+    flush_stats(o, s_hist, s_flops, s_annz);
+}
+
+// One 256-thread workgroup per queued long row, grid-stride over the queue.
+__global__ void __launch_bounds__(256) k_rowinfo_long(Csr A, Csr B, int64_t k_lo, int64_t k_hi,
+                                                      int full_window, BinParams bp,
+                                                      RowInfoOut o) {
+    __shared__ int s_hist[NBINS];
+    __shared__ int64_t s_flops[NBINS], s_annz[NBINS];
+    __shared__ int64_t s_red[8];
+    __shared__ int32_t s_redm[8];
+    if (threadIdx.x < NBINS) {
+        s_hist[threadIdx.x] = 0;
+        s_flops[threadIdx.x] = 0;
+        s_annz[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int nq = *o.long_count;
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int64_t i = o.long_rows[q];
+        int64_t beg = A.rp[i], end = A.rp[i + 1];
+        if (!full_window) {
+            beg = lower_bound_col(A.col, beg, end, k_lo);
+            end = lower_bound_col(A.col, beg, end, k_hi);
+        }
+        int64_t f = 0;
+        int32_t mb = 0;
+        for (int64_t p = beg + threadIdx.x; p < end; p += 256) {
+            int64_t k = A.col[p];
+            int64_t len = B.rp[k + 1] - B.rp[k];
+            f += len;
+            mb = len > mb ? (int32_t)len : mb;
+        }
+        f = wave_reduce_add(f);
+        mb = wave_reduce_max(mb);
+        const int w = threadIdx.x / SPG_WAVE;
+        if (lane_id() == 0) {
+            s_red[w] = f;
+            s_redm[w] = mb;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t tf = 0;
+            int32_t tm = 0;
+            for (int x = 0; x < 4; ++x) {
+                tf += s_red[x];
+                tm = s_redm[x] > tm ? s_redm[x] : tm;
+            }
+            finish_row(i, beg, end, tf, tm, bp, o, s_hist, s_flops, s_annz);
+        }
+        __syncthreads();
+    }
+    flush_stats(o, s_hist, s_flops, s_annz);
+}
+
+// Numeric classification from exact counts (after the symbolic scan).
+__global__ void __launch_bounds__(256) k_num_classify(int64_t m, const int64_t* c_rp,
+                                                      const int64_t* a_beg, const int64_t* a_end,
+                                                      const int64_t* flops, BinParams bp,
+                                                      uint8_t* bin, int64_t* bin_stats) {
+    __shared__ int s_hist[NBINS];
+    __shared__ int64_t s_flops[NBINS], s_annz[NBINS], s_cnnz[NBINS];
+    if (threadIdx.x < NBINS) {
+        s_hist[threadIdx.x] = 0;
+        s_flops[threadIdx.x] = 0;
+        s_annz[threadIdx.x] = 0;
+        s_cnnz[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) {
+        int64_t cnt = c_rp[i + 1] - c_rp[i];
+        int64_t an = a_end[i] - a_beg[i];
+        int64_t f = flops[i];
+        int b = num_bin(f, an, cnt, bp);
+        bin[i] = (uint8_t)b;
+        atomicAdd(&s_hist[b], 1);
+        atomicAdd((unsigned long long*)&s_flops[b], (unsigned long long)f);
+        atomicAdd((unsigned long long*)&s_annz[b], (unsigned long long)an);
+        atomicAdd((unsigned long long*)&s_cnnz[b], (unsigned long long)cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x < NBINS) {
+        int b = threadIdx.x;
+        if (s_hist[b]) {
+            atomicAdd((unsigned long long*)&bin_stats[b], (unsigned long long)s_hist[b]);
+            atomicAdd((unsigned long long*)&bin_stats[NBINS + b], (unsigned long long)s_flops[b]);
+            atomicAdd((unsigned long long*)&bin_stats[2 * NBINS + b], (unsigned long long)s_annz[b]);
+            atomicAdd((unsigned long long*)&bin_stats[3 * NBINS + b], (unsigned long long)s_cnnz[b]);
+        }
+    }
+}
+
+// Counting-sort scatter of rows into per-bin lists.  bin_stats[0..NBINS)
+// holds the per-bin row counts; list segment of bin b starts at the sum of
+// the counts of bins < b.  cursor[NBINS] must be zero on entry.
+__global__ void __launch_bounds__(256) k_bin_scatter(int64_t m, const uint8_t* bin,
+                                                     const int64_t* bin_counts, int32_t* cursor,
+                                                     int32_t* lists) {
+    __shared__ int s_cnt[NBINS];
+    __shared__ int s_base[NBINS];
+    if (threadIdx.x < NBINS) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int b = -1, local = 0;
+    if (i < m) {
+        b = bin[i];
+        local = atomicAdd(&s_cnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < NBINS) {
+        int bb = threadIdx.x;
+        int64_t off = 0;
+        for (int x = 0; x < bb; ++x) off += bin_counts[x];
+        s_base[bb] = s_cnt[bb] ? (int)off + atomicAdd(&cursor[bb], s_cnt[bb]) : 0;
+    }
+    __syncthreads();
+    if (b >= 0) lists[s_base[b] + local] = (int32_t)i;
+}
+
+}  // namespace spg

@@ -1,0 +1,808 @@
+// Host side of the C ABI declared in include/spgemm.h: argument checks,
+// plan-owned scratch, bin dispatch, launches and profiling.  All device work
+// is in the kernels included below.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spgemm.h"
+#include "merge.hpp"
+#include "numeric.hpp"
+#include "rowinfo.hpp"
+#include "scan.hpp"
+#include "symbolic.hpp"
+
+using namespace spg;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static spg_status fail(spg_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return fail(SPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+#define SPG_TRY(expr)                      \
+    do {                                   \
+        spg_status _s = (expr);            \
+        if (_s != SPG_OK) return _s;       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device scratch that only grows
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    spg_status ensure(size_t need, const char* what) {
+        if (need <= bytes) return SPG_OK;
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t want = std::max(need, (size_t)256);
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            hipGetLastError();
+            return fail(SPG_ERR_OOM, std::string("device allocation failed: ") + what);
+        }
+        bytes = want;
+        return SPG_OK;
+    }
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t beg, end;
+};
+
+struct Signature {
+    const void *a_rp = nullptr, *a_col = nullptr, *b_rp = nullptr, *b_col = nullptr;
+    int64_t m = -1, n = -1, k = -1, annz = -1, bnnz = -1, k_lo = -1, k_hi = -1;
+    bool operator==(const Signature& o) const {
+        return a_rp == o.a_rp && a_col == o.a_col && b_rp == o.b_rp && b_col == o.b_col && m == o.m &&
+               n == o.n && k == o.k && annz == o.annz && bnnz == o.bnnz && k_lo == o.k_lo &&
+               k_hi == o.k_hi;
+    }
+};
+
+struct spg_plan_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    spg_opts opts;
+    int max_lds = 65536;
+
+    // per-row state of the current product
+    DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
+    DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr;
+    int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
+    LayerDesc* h_layers = nullptr; // pinned staging for merge descriptors
+    int h_layers_cap = 0;
+
+    Signature sig;
+    bool have_symbolic = false;
+    bool num_counts_valid = false;
+    int64_t sym_counts[3 * NBINS];
+    int64_t num_counts[4 * NBINS];
+    int64_t last_flops = 0, last_nnz = -1;
+    int dense_chunks = 0;
+
+    // merge state
+    std::vector<LayerDesc> merge_sig;
+    int64_t merge_m = -1, merge_n = -1;
+    int64_t merge_counts[2 * NBINS];
+
+    // profiling
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<spg_kernel_time> prof_acc;
+};
+
+// ---------------------------------------------------------------------------
+// launch helper: optional per-launch events, error check
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(spg_plan P) {
+    if (!P->event_pool.empty()) {
+        hipEvent_t e = P->event_pool.back();
+        P->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+template <class F>
+static spg_status launch(spg_plan P, const std::string& name, F&& f) {
+    hipEvent_t b = nullptr, e = nullptr;
+    if (P->opts.profile) {
+        b = take_event(P);
+        e = take_event(P);
+        hipEventRecord(b, P->stream);
+    }
+    f();
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(SPG_ERR_HIP, std::string("launch ") + name + ": " + hipGetErrorString(err));
+    if (P->opts.profile) {
+        hipEventRecord(e, P->stream);
+        P->prof_pending.push_back({name, b, e});
+    }
+    return SPG_OK;
+}
+
+static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// ---------------------------------------------------------------------------
+// public helpers
+// ---------------------------------------------------------------------------
+extern "C" void spg_default_opts(spg_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->validate = 0;
+    o->small_max_flops = 64;
+    o->hash_max_flops = 8192;
+    o->hash_max_nnz = 2048;
+    o->dense_chunk_cols = 8192;
+    o->profile = 0;
+}
+
+extern "C" const char* spg_status_string(spg_status s) {
+    switch (s) {
+        case SPG_OK: return "SPG_OK";
+        case SPG_ERR_ARG: return "SPG_ERR_ARG";
+        case SPG_ERR_SHAPE: return "SPG_ERR_SHAPE";
+        case SPG_ERR_NOT_CANONICAL: return "SPG_ERR_NOT_CANONICAL";
+        case SPG_ERR_INDEX_RANGE: return "SPG_ERR_INDEX_RANGE";
+        case SPG_ERR_OOM: return "SPG_ERR_OOM";
+        case SPG_ERR_CAPACITY: return "SPG_ERR_CAPACITY";
+        case SPG_ERR_HIP: return "SPG_ERR_HIP";
+        case SPG_ERR_STATE: return "SPG_ERR_STATE";
+    }
+    return "SPG_ERR_UNKNOWN";
+}
+
+extern "C" const char* spg_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opts* opts) {
+    if (!out) return fail(SPG_ERR_ARG, "plan pointer is NULL");
+    *out = nullptr;
+    spg_plan P = new (std::nothrow) spg_plan_s();
+    if (!P) return fail(SPG_ERR_OOM, "host allocation failed");
+    spg_default_opts(&P->opts);
+    if (opts) {
+        spg_opts d = P->opts;
+        P->opts = *opts;
+        if (!P->opts.small_max_flops) P->opts.small_max_flops = d.small_max_flops;
+        if (!P->opts.hash_max_flops) P->opts.hash_max_flops = d.hash_max_flops;
+        if (!P->opts.hash_max_nnz) P->opts.hash_max_nnz = d.hash_max_nnz;
+        if (!P->opts.dense_chunk_cols) P->opts.dense_chunk_cols = d.dense_chunk_cols;
+    }
+    if (P->opts.small_max_flops < 0 || P->opts.small_max_flops > 64) {
+        delete P;
+        return fail(SPG_ERR_ARG, "small_max_flops must be in [0, 64]");
+    }
+    if (P->opts.hash_max_flops < 1 || P->opts.hash_max_flops > 8192) {
+        delete P;
+        return fail(SPG_ERR_ARG, "hash_max_flops must be in [1, 8192]");
+    }
+    if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 2048) {
+        delete P;
+        return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 2048]");
+    }
+    if (P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096) {
+        delete P;
+        return fail(SPG_ERR_ARG, "dense_chunk_cols must be 4096 or 8192");
+    }
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(SPG_ERR_HIP, "hipGetDevice failed");
+    }
+    P->stream = (hipStream_t)stream;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
+        P->max_lds = lds;
+    if (hipHostMalloc((void**)&P->h_stats, sizeof(int64_t) * (4 * NBINS + 8), hipHostMallocDefault) != hipSuccess) {
+        delete P;
+        hipGetLastError();
+        return fail(SPG_ERR_OOM, "pinned host allocation failed");
+    }
+    // LDS beyond 64 KiB for the dynamic-bitmap kernel
+    hipFuncSetAttribute((const void*)k_sym_bitmap<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        std::max(0, P->max_lds - (int)sizeof(ProductLds<512>) - 64));
+    hipGetLastError();
+    *out = P;
+    return SPG_OK;
+}
+
+extern "C" spg_status spg_plan_destroy(spg_plan P) {
+    if (!P) return SPG_OK;
+    hipStreamSynchronize(P->stream);
+    for (DevBuf* b : {&P->a_beg, &P->a_end, &P->flops, &P->maxb, &P->bin, &P->lists, &P->long_rows,
+                      &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
+                      &P->mbin, &P->mlists, &P->mstats, &P->mctr})
+        b->release();
+    if (P->h_stats) hipHostFree(P->h_stats);
+    if (P->h_layers) hipHostFree(P->h_layers);
+    for (auto& r : P->prof_pending) {
+        hipEventDestroy(r.beg);
+        hipEventDestroy(r.end);
+    }
+    for (auto e : P->event_pool) hipEventDestroy(e);
+    delete P;
+    return SPG_OK;
+}
+
+extern "C" spg_status spg_plan_set_stream(spg_plan P, void* stream) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->stream = (hipStream_t)stream;
+    return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+static spg_status check_csr(const spg_csr* M, const char* name, spg_semiring sr, bool need_val) {
+    if (!M) return fail(SPG_ERR_ARG, std::string(name) + " is NULL");
+    if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0)
+        return fail(SPG_ERR_ARG, std::string(name) + ": negative dimension or nnz");
+    if (M->nrows >= (1ll << 31) - 1 || M->ncols >= (1ll << 31) - 1)
+        return fail(SPG_ERR_INDEX_RANGE, std::string(name) + ": dimension >= 2^31");
+    if (!M->row_ptr) return fail(SPG_ERR_ARG, std::string(name) + ".row_ptr is NULL");
+    if (M->nnz > 0 && !M->col) return fail(SPG_ERR_ARG, std::string(name) + ".col is NULL");
+    if (need_val && M->nnz > 0 && !M->val && sr != SPG_SR_OR_AND_BOOL)
+        return fail(SPG_ERR_ARG, std::string(name) + ".val is NULL");
+    return SPG_OK;
+}
+
+static Csr view(const spg_csr* M) { return Csr{M->nrows, M->ncols, M->nnz, M->row_ptr, M->col, M->val}; }
+
+// validation: row_ptr[0]==0, nondecreasing, row_ptr[m]==nnz, columns in range and increasing
+__global__ void __launch_bounds__(256) k_validate(Csr M, int32_t* bad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M.nrows) return;
+    const int64_t s = M.rp[i], e = M.rp[i + 1];
+    bool ok = s <= e && s >= 0 && e <= M.nnz;
+    if (i == 0 && s != 0) ok = false;
+    if (i == M.nrows - 1 && e != M.nnz) ok = false;
+    if (ok) {
+        int64_t prev = -1;
+        for (int64_t p = s; p < e; ++p) {
+            int64_t c = M.col[p];
+            if (c <= prev || c >= M.ncols) { ok = false; break; }
+            prev = c;
+        }
+    }
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static spg_status fill_i32(spg_plan P, int32_t* p, int64_t n, int32_t v) {
+    if (n <= 0) return SPG_OK;
+    return launch(P, "fill", [&] { k_fill_i32<<<grid_for(n, 256), 256, 0, P->stream>>>(p, n, v); });
+}
+static spg_status fill_i64(spg_plan P, int64_t* p, int64_t n, int64_t v) {
+    if (n <= 0) return SPG_OK;
+    return launch(P, "fill", [&] { k_fill_i64<<<grid_for(n, 256), 256, 0, P->stream>>>(p, n, v); });
+}
+
+static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
+    if (M->nrows == 0) return SPG_OK;
+    SPG_TRY(P->small_i32.ensure(64, "flags"));
+    int32_t* bad = P->small_i32.as<int32_t>() + 32;
+    SPG_TRY(fill_i32(P, bad, 1, 0));
+    Csr v = view(M);
+    SPG_TRY(launch(P, "validate", [&] { k_validate<<<grid_for(M->nrows, 256), 256, 0, P->stream>>>(v, bad); }));
+    int32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    if (h) return fail(SPG_ERR_NOT_CANONICAL, std::string(name) + " is not canonical CSR");
+    return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scan of counts (in place over rp[1..m]); rp[0] = 0
+// ---------------------------------------------------------------------------
+static spg_status scan_counts(spg_plan P, int64_t* rp, int64_t m) {
+    SPG_TRY(fill_i64(P, rp, 1, 0));
+    if (m == 0) return SPG_OK;
+    const int64_t ntiles = (m + SCAN_TILE - 1) / SCAN_TILE;
+    SPG_TRY(P->tiles.ensure(sizeof(int64_t) * (ntiles + 1), "scan tiles"));
+    int64_t* tiles = P->tiles.as<int64_t>();
+    int64_t* cnt = rp + 1;
+    SPG_TRY(launch(P, "scan", [&] { k_scan_tiles<<<(unsigned)ntiles, SCAN_NT, 0, P->stream>>>(cnt, m, tiles); }));
+    SPG_TRY(launch(P, "scan", [&] { k_scan_top<<<1, SCAN_NT, 0, P->stream>>>(tiles, ntiles); }));
+    SPG_TRY(launch(P, "scan", [&] { k_scan_apply<<<(unsigned)ntiles, SCAN_NT, 0, P->stream>>>(cnt, m, tiles, cnt); }));
+    return SPG_OK;
+}
+
+static spg_status ensure_rows(spg_plan P, int64_t m) {
+    const size_t mm = (size_t)std::max<int64_t>(m, 1);
+    SPG_TRY(P->a_beg.ensure(8 * mm, "a_beg"));
+    SPG_TRY(P->a_end.ensure(8 * mm, "a_end"));
+    SPG_TRY(P->flops.ensure(8 * mm, "flops"));
+    SPG_TRY(P->maxb.ensure(4 * mm, "maxb"));
+    SPG_TRY(P->bin.ensure(mm, "bin"));
+    SPG_TRY(P->lists.ensure(4 * mm, "bin lists"));
+    SPG_TRY(P->long_rows.ensure(4 * mm, "long rows"));
+    SPG_TRY(P->small_i32.ensure(64 * 4, "counters"));
+    SPG_TRY(P->stats.ensure(sizeof(int64_t) * 4 * NBINS, "bin stats"));
+    return SPG_OK;
+}
+
+static BinParams bin_params(spg_plan P, int64_t n) {
+    BinParams bp;
+    bp.small_max_flops = P->opts.small_max_flops;
+    bp.hash_max_flops = P->opts.hash_max_flops;
+    bp.hash_max_nnz = P->opts.hash_max_nnz;
+    const int64_t bitmap_bytes = ((n + 31) / 32) * 4;
+    bp.dense_ok = (n <= (1 << 19)) && (bitmap_bytes + (int64_t)sizeof(ProductLds<512>) + 256 <= P->max_lds);
+    bp.ncols = n;
+    return bp;
+}
+
+// ---------------------------------------------------------------------------
+// symbolic
+// ---------------------------------------------------------------------------
+template <int NT, int LOG2T>
+static spg_status launch_sym_hash(spg_plan P, Csr A, Csr B, const int32_t* rows, int64_t nr, int64_t* cnt) {
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    return launch(P, "sym_hash" + std::to_string(1 << LOG2T), [&] {
+        k_sym_hash<NT, LOG2T><<<(unsigned)nr, NT, 0, P->stream>>>(A, B, rows, ab, ae, cnt);
+    });
+}
+
+static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int32_t* rows, int64_t nr, int64_t* cnt) {
+    switch (lg) {
+        case 7: return launch_sym_hash<64, 7>(P, A, B, rows, nr, cnt);
+        case 8: return launch_sym_hash<64, 8>(P, A, B, rows, nr, cnt);
+        case 9: return launch_sym_hash<128, 9>(P, A, B, rows, nr, cnt);
+        case 10: return launch_sym_hash<256, 10>(P, A, B, rows, nr, cnt);
+        case 11: return launch_sym_hash<256, 11>(P, A, B, rows, nr, cnt);
+        case 12: return launch_sym_hash<512, 12>(P, A, B, rows, nr, cnt);
+        case 13: return launch_sym_hash<512, 13>(P, A, B, rows, nr, cnt);
+        case 14: return launch_sym_hash<1024, 14>(P, A, B, rows, nr, cnt);
+    }
+    return fail(SPG_ERR_ARG, "bad hash bin");
+}
+
+extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B,
+                                      int64_t k_lo, int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    SPG_TRY(check_csr(A, "A", sr, false));
+    SPG_TRY(check_csr(B, "B", sr, false));
+    if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
+    if (k_lo < 0 || k_hi < k_lo || k_hi > A->ncols) return fail(SPG_ERR_ARG, "window must satisfy 0 <= k_lo <= k_hi <= A.ncols");
+    if (!c_row_ptr) return fail(SPG_ERR_ARG, "c_row_ptr is NULL");
+    P->have_symbolic = false;
+    P->num_counts_valid = false;
+    const int64_t m = A->nrows, n = B->ncols;
+    if (P->opts.validate) {
+        SPG_TRY(validate_csr(P, A, "A"));
+        SPG_TRY(validate_csr(P, B, "B"));
+    }
+    SPG_TRY(ensure_rows(P, m));
+    Csr a = view(A), b = view(B);
+    BinParams bp = bin_params(P, n);
+    int64_t* stats = P->stats.as<int64_t>();
+    int32_t* ctr = P->small_i32.as<int32_t>();  // [0] long count, [1..NBINS] cursors
+    int64_t* cnt = c_row_ptr + 1;
+    const int full = (k_lo == 0 && k_hi == A->ncols) ? 1 : 0;
+
+    SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
+    SPG_TRY(fill_i32(P, ctr, 1 + NBINS, 0));
+    RowInfoOut o{P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), P->flops.as<int64_t>(), P->maxb.as<int32_t>(),
+                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr};
+    if (m > 0) {
+        SPG_TRY(launch(P, "rowinfo", [&] {
+            k_rowinfo<<<grid_for(m, 16), 256, 0, P->stream>>>(a, b, k_lo, k_hi, full, bp, o);
+        }));
+        SPG_TRY(launch(P, "rowinfo_long", [&] {
+            k_rowinfo_long<<<256, 256, 0, P->stream>>>(a, b, k_lo, k_hi, full, bp, o);
+        }));
+        SPG_TRY(launch(P, "bin_scatter", [&] {
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, P->stream>>>(m, P->bin.as<uint8_t>(), stats, ctr + 1,
+                                                                   P->lists.as<int32_t>());
+        }));
+    }
+    HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 3 * NBINS, hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    std::memcpy(P->sym_counts, P->h_stats, sizeof(int64_t) * 3 * NBINS);
+    int64_t tot = 0;
+    for (int x = 0; x < NBINS; ++x) tot += P->sym_counts[NBINS + x];
+    P->last_flops = tot;
+    if (P->sym_counts[BIN_DENSE] > 0 && !bp.dense_ok)
+        return fail(SPG_ERR_INDEX_RANGE, "rows with more products than the hash limit need n <= 2^19 columns");
+
+    // per-bin accumulators
+    const int32_t* lists = P->lists.as<int32_t>();
+    int64_t off = 0;
+    for (int bb = 0; bb < NBINS; ++bb) {
+        const int64_t nr = P->sym_counts[bb];
+        const int32_t* rows = lists + off;
+        off += nr;
+        if (nr == 0 || bb == BIN_EMPTY || bb == BIN_TINY) continue;
+        if (bb == BIN_SMALL) {
+            SPG_TRY(launch(P, "sym_small", [&] {
+                k_sym_small<<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
+                                                                     P->a_end.as<int64_t>(), cnt);
+            }));
+        } else if (bb == BIN_DENSE) {
+            const int32_t nwords = (int32_t)((n + 31) / 32);
+            SPG_TRY(launch(P, "sym_bitmap", [&] {
+                k_sym_bitmap<512><<<(unsigned)nr, 512, (size_t)nwords * 4, P->stream>>>(
+                    a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords);
+            }));
+        } else {
+            SPG_TRY(sym_hash_dispatch(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, cnt));
+        }
+    }
+    SPG_TRY(scan_counts(P, c_row_ptr, m));
+
+    // numeric classification from the exact counts
+    int64_t* nstats = stats + 0;  // reuse: symbolic stats already copied out
+    SPG_TRY(fill_i64(P, nstats, 4 * NBINS, 0));
+    SPG_TRY(fill_i32(P, ctr + 1, NBINS, 0));
+    if (m > 0) {
+        SPG_TRY(launch(P, "num_classify", [&] {
+            k_num_classify<<<grid_for(m, 256), 256, 0, P->stream>>>(m, c_row_ptr, P->a_beg.as<int64_t>(),
+                                                                    P->a_end.as<int64_t>(), P->flops.as<int64_t>(),
+                                                                    bp, P->bin.as<uint8_t>(), nstats);
+        }));
+        SPG_TRY(launch(P, "bin_scatter", [&] {
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, P->stream>>>(m, P->bin.as<uint8_t>(), nstats, ctr + 1,
+                                                                   P->lists.as<int32_t>());
+        }));
+    }
+    Signature s;
+    s.a_rp = A->row_ptr; s.a_col = A->col; s.b_rp = B->row_ptr; s.b_col = B->col;
+    s.m = m; s.n = n; s.k = A->ncols; s.annz = A->nnz; s.bnnz = B->nnz; s.k_lo = k_lo; s.k_hi = k_hi;
+    P->sig = s;
+    P->have_symbolic = true;
+    if (c_nnz) {
+        HIP_TRY(hipMemcpyAsync(P->h_stats, nstats, sizeof(int64_t) * 4 * NBINS, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipMemcpyAsync(P->h_stats + 4 * NBINS, c_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        std::memcpy(P->num_counts, P->h_stats, sizeof(int64_t) * 4 * NBINS);
+        P->last_nnz = P->h_stats[4 * NBINS];
+        *c_nnz = P->last_nnz;
+        P->num_counts_valid = true;
+    }
+    return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// numeric
+// ---------------------------------------------------------------------------
+template <int SR, int NT, int LOG2T>
+static spg_status launch_num_hash(spg_plan P, Csr A, Csr B, const int32_t* rows, int64_t nr,
+                                  const int64_t* crp, int32_t* ccol, void* cval) {
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    return launch(P, "num_hash" + std::to_string(1 << LOG2T), [&] {
+        k_num_hash<SR, NT, LOG2T><<<(unsigned)nr, NT, 0, P->stream>>>(A, B, rows, ab, ae, crp, ccol, cval);
+    });
+}
+
+template <int SR>
+static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int32_t* rows, int64_t nr,
+                                    const int64_t* crp, int32_t* ccol, void* cval) {
+    switch (lg) {
+        case 7: return launch_num_hash<SR, 64, 7>(P, A, B, rows, nr, crp, ccol, cval);
+        case 8: return launch_num_hash<SR, 64, 8>(P, A, B, rows, nr, crp, ccol, cval);
+        case 9: return launch_num_hash<SR, 128, 9>(P, A, B, rows, nr, crp, ccol, cval);
+        case 10: return launch_num_hash<SR, 256, 10>(P, A, B, rows, nr, crp, ccol, cval);
+        case 11: return launch_num_hash<SR, 256, 11>(P, A, B, rows, nr, crp, ccol, cval);
+        case 12: return launch_num_hash<SR, 256, 12>(P, A, B, rows, nr, crp, ccol, cval);
+    }
+    return fail(SPG_ERR_ARG, "bad numeric hash bin");
+}
+
+template <int SR>
+static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32_t* ccol, void* cval) {
+    const int32_t* lists = P->lists.as<int32_t>();
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    const int W = P->opts.dense_chunk_cols;
+    int64_t off = 0;
+    for (int bb = 0; bb < NBINS; ++bb) {
+        const int64_t nr = P->num_counts[bb];
+        const int32_t* rows = lists + off;
+        off += nr;
+        if (nr == 0 || bb == BIN_EMPTY) continue;
+        if (bb == BIN_TINY) {
+            SPG_TRY(launch(P, "num_tiny", [&] {
+                k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, ab, crp, ccol, cval);
+            }));
+        } else if (bb == BIN_SMALL) {
+            SPG_TRY(launch(P, "num_small", [&] {
+                k_num_small<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval);
+            }));
+        } else if (bb == BIN_DENSE) {
+            const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
+            P->dense_chunks = chunks;
+            const int32_t* split = nullptr;
+            if (chunks > 1) {
+                const int64_t entries = b.nrows * (int64_t)(chunks + 1);
+                SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
+                int32_t* sp = P->split.as<int32_t>();
+                if (entries > 0) {
+                    SPG_TRY(launch(P, "split_table", [&] {
+                        k_split_table<<<grid_for(entries, 256), 256, 0, P->stream>>>(b, W, chunks, sp);
+                    }));
+                }
+                split = sp;
+            }
+            if (W == 8192) {
+                SPG_TRY(launch(P, "num_dense", [&] {
+                    k_num_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks,
+                                                                                    crp, ccol, cval);
+                }));
+            } else {
+                SPG_TRY(launch(P, "num_dense", [&] {
+                    k_num_dense<SR, 512, 4096><<<(unsigned)nr, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks,
+                                                                                    crp, ccol, cval);
+                }));
+            }
+        } else {
+            SPG_TRY(num_hash_dispatch<SR>(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, crp, ccol, cval));
+        }
+    }
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_numeric(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B,
+                                     int64_t k_lo, int64_t k_hi, const int64_t* c_row_ptr, int32_t* c_col,
+                                     void* c_val) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    SPG_TRY(check_csr(A, "A", sr, c_val != nullptr));
+    SPG_TRY(check_csr(B, "B", sr, c_val != nullptr));
+    if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
+    if (!c_row_ptr) return fail(SPG_ERR_ARG, "c_row_ptr is NULL");
+    Signature s;
+    s.a_rp = A->row_ptr; s.a_col = A->col; s.b_rp = B->row_ptr; s.b_col = B->col;
+    s.m = A->nrows; s.n = B->ncols; s.k = A->ncols; s.annz = A->nnz; s.bnnz = B->nnz; s.k_lo = k_lo; s.k_hi = k_hi;
+    if (!P->have_symbolic || !(s == P->sig))
+        return fail(SPG_ERR_STATE, "spgemm_numeric needs the matching spgemm_symbolic on this plan first");
+    if (!P->num_counts_valid) {
+        HIP_TRY(hipMemcpyAsync(P->h_stats, P->stats.p, sizeof(int64_t) * 4 * NBINS, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipMemcpyAsync(P->h_stats + 4 * NBINS, c_row_ptr + s.m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        std::memcpy(P->num_counts, P->h_stats, sizeof(int64_t) * 4 * NBINS);
+        P->last_nnz = P->h_stats[4 * NBINS];
+        P->num_counts_valid = true;
+    }
+    if (P->last_nnz > 0 && !c_col) return fail(SPG_ERR_ARG, "c_col is NULL");
+    Csr a = view(A), b = view(B);
+    switch (sr) {
+        case SPG_SR_PLUS_TIMES_F64: return numeric_sr<SR_F64>(P, a, b, c_row_ptr, c_col, c_val);
+        case SPG_SR_PLUS_TIMES_I64: return numeric_sr<SR_I64>(P, a, b, c_row_ptr, c_col, c_val);
+        case SPG_SR_OR_AND_BOOL: return numeric_sr<SR_BOOL>(P, a, b, c_row_ptr, c_col, c_val);
+    }
+    return fail(SPG_ERR_ARG, "unknown semiring");
+}
+
+// ---------------------------------------------------------------------------
+// merge
+// ---------------------------------------------------------------------------
+template <int SR>
+static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, const int64_t* orp, int32_t* ocol,
+                               void* oval) {
+    const LayerDesc* d = P->layer_desc.as<LayerDesc>();
+    const int32_t* lists = P->mlists.as<int32_t>();
+    const int64_t* tl = P->merge_len.as<int64_t>();
+    int64_t off = 0;
+    for (int bb = 0; bb < 4; ++bb) {
+        const int64_t nr = P->merge_counts[bb];
+        const int32_t* rows = lists + off;
+        off += nr;
+        if (nr == 0 || bb == MBIN_EMPTY) continue;
+        if (bb == MBIN_SMALL) {
+            SPG_TRY(launch(P, "merge_small", [&] {
+                k_merge_small<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(c, d, rows, (int32_t)nr, cnt, orp, ocol, oval);
+            }));
+        } else if (bb == MBIN_LDS) {
+            SPG_TRY(launch(P, "merge_lds", [&] {
+                k_merge_lds<SR, 256><<<(unsigned)nr, 256, 0, P->stream>>>(c, d, rows, tl, cnt, orp, ocol, oval);
+            }));
+        } else {
+            SPG_TRY(launch(P, "merge_dense", [&] {
+                k_merge_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, P->stream>>>(c, d, rows, n, cnt, orp, ocol, oval);
+            }));
+        }
+    }
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t nlayers, const spg_csr* layers,
+                                          int64_t* out_row_ptr, int32_t* out_col, void* out_val, int64_t* out_nnz) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    if (nlayers < 1 || nlayers > 64) return fail(SPG_ERR_ARG, "nlayers must be in [1, 64]");
+    if (!layers || !out_row_ptr) return fail(SPG_ERR_ARG, "layers or out_row_ptr is NULL");
+    const bool count_pass = out_col == nullptr;
+    const int64_t m = layers[0].nrows, n = layers[0].ncols;
+    for (int l = 0; l < nlayers; ++l) {
+        SPG_TRY(check_csr(&layers[l], "layer", sr, !count_pass && out_val != nullptr));
+        if (layers[l].nrows != m || layers[l].ncols != n) return fail(SPG_ERR_SHAPE, "layer shapes differ");
+    }
+    if (count_pass && !out_nnz) return fail(SPG_ERR_ARG, "count pass needs out_nnz");
+    std::vector<LayerDesc> desc(nlayers);
+    for (int l = 0; l < nlayers; ++l) desc[l] = LayerDesc{layers[l].row_ptr, layers[l].col, layers[l].val};
+    if (P->opts.validate && count_pass)
+        for (int l = 0; l < nlayers; ++l) SPG_TRY(validate_csr(P, &layers[l], "layer"));
+    int64_t* cnt = out_row_ptr + 1;
+    if (count_pass) {
+        const size_t mm = (size_t)std::max<int64_t>(m, 1);
+        SPG_TRY(P->merge_len.ensure(8 * mm, "merge lengths"));
+        SPG_TRY(P->mbin.ensure(mm, "merge bins"));
+        SPG_TRY(P->mlists.ensure(4 * mm, "merge lists"));
+        SPG_TRY(P->mstats.ensure(sizeof(int64_t) * 4 * NBINS, "merge stats"));
+        SPG_TRY(P->mctr.ensure(sizeof(int32_t) * 64, "merge counters"));
+        SPG_TRY(P->layer_desc.ensure(sizeof(LayerDesc) * 64, "layer descriptors"));
+        if (P->h_layers_cap < 64) {
+            if (P->h_layers) hipHostFree(P->h_layers);
+            P->h_layers = nullptr;
+            HIP_TRY(hipHostMalloc((void**)&P->h_layers, sizeof(LayerDesc) * 64, hipHostMallocDefault));
+            P->h_layers_cap = 64;
+        }
+        // the previous user of the staging buffer has finished: every merge call ends with a sync
+        std::memcpy(P->h_layers, desc.data(), sizeof(LayerDesc) * nlayers);
+        HIP_TRY(hipMemcpyAsync(P->layer_desc.p, P->h_layers, sizeof(LayerDesc) * nlayers, hipMemcpyHostToDevice, P->stream));
+        int64_t* stats = P->mstats.as<int64_t>();
+        int32_t* ctr = P->mctr.as<int32_t>();
+        SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
+        SPG_TRY(fill_i32(P, ctr, NBINS, 0));
+        if (m > 0) {
+            SPG_TRY(launch(P, "merge_rowinfo", [&] {
+                k_merge_rowinfo<<<grid_for(m, 256), 256, 0, P->stream>>>(m, nlayers, P->layer_desc.as<LayerDesc>(),
+                                                                        P->merge_len.as<int64_t>(), P->mbin.as<uint8_t>(),
+                                                                        stats);
+            }));
+            SPG_TRY(launch(P, "bin_scatter", [&] {
+                k_bin_scatter<<<grid_for(m, 256), 256, 0, P->stream>>>(m, P->mbin.as<uint8_t>(), stats, ctr,
+                                                                       P->mlists.as<int32_t>());
+            }));
+        }
+        HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 2 * NBINS, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        std::memcpy(P->merge_counts, P->h_stats, sizeof(int64_t) * 2 * NBINS);
+        P->merge_sig = desc;
+        P->merge_m = m;
+        P->merge_n = n;
+        // EMPTY rows count zero
+        SPG_TRY(fill_i64(P, cnt, m, 0));
+        spg_status st = SPG_OK;
+        switch (sr) {
+            case SPG_SR_PLUS_TIMES_F64: st = merge_launch<SR_F64>(P, nlayers, n, cnt, nullptr, nullptr, nullptr); break;
+            case SPG_SR_PLUS_TIMES_I64: st = merge_launch<SR_I64>(P, nlayers, n, cnt, nullptr, nullptr, nullptr); break;
+            case SPG_SR_OR_AND_BOOL: st = merge_launch<SR_BOOL>(P, nlayers, n, cnt, nullptr, nullptr, nullptr); break;
+        }
+        SPG_TRY(st);
+        SPG_TRY(scan_counts(P, out_row_ptr, m));
+        HIP_TRY(hipMemcpyAsync(P->h_stats, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        *out_nnz = P->h_stats[0];
+        return SPG_OK;
+    }
+    // fill pass: must follow the count pass over the same layers
+    bool same = P->merge_m == m && P->merge_n == n && (int)P->merge_sig.size() == nlayers;
+    for (int l = 0; same && l < nlayers; ++l)
+        same = P->merge_sig[l].rp == desc[l].rp && P->merge_sig[l].col == desc[l].col;
+    if (!same) return fail(SPG_ERR_STATE, "merge fill pass needs the matching count pass first");
+    // values may differ from the count pass (they were not needed there)
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    std::memcpy(P->h_layers, desc.data(), sizeof(LayerDesc) * nlayers);
+    HIP_TRY(hipMemcpyAsync(P->layer_desc.p, P->h_layers, sizeof(LayerDesc) * nlayers, hipMemcpyHostToDevice, P->stream));
+    spg_status st = SPG_OK;
+    switch (sr) {
+        case SPG_SR_PLUS_TIMES_F64: st = merge_launch<SR_F64>(P, nlayers, n, nullptr, out_row_ptr, out_col, out_val); break;
+        case SPG_SR_PLUS_TIMES_I64: st = merge_launch<SR_I64>(P, nlayers, n, nullptr, out_row_ptr, out_col, out_val); break;
+        case SPG_SR_OR_AND_BOOL: st = merge_launch<SR_BOOL>(P, nlayers, n, nullptr, out_row_ptr, out_col, out_val); break;
+    }
+    SPG_TRY(st);
+    if (out_nnz) {
+        HIP_TRY(hipMemcpyAsync(P->h_stats, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        *out_nnz = P->h_stats[0];
+    }
+    return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stats and profiling
+// ---------------------------------------------------------------------------
+extern "C" spg_status spg_plan_stats(spg_plan P, spg_stats* out) {
+    if (!P || !out) return fail(SPG_ERR_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->m = P->sig.m;
+    out->n = P->sig.n;
+    out->k = P->sig.k;
+    out->flops = P->last_flops;
+    out->nnz_c = P->last_nnz;
+    for (int b = 0; b < NBINS; ++b) {
+        out->sym_rows[b] = P->sym_counts[b];
+        out->sym_flops[b] = P->sym_counts[NBINS + b];
+        out->sym_annz[b] = P->sym_counts[2 * NBINS + b];
+        if (P->num_counts_valid) {
+            out->num_rows[b] = P->num_counts[b];
+            out->num_flops[b] = P->num_counts[NBINS + b];
+            out->num_annz[b] = P->num_counts[2 * NBINS + b];
+            out->num_cnnz[b] = P->num_counts[3 * NBINS + b];
+        }
+    }
+    out->dense_chunk_cols = P->opts.dense_chunk_cols;
+    out->dense_chunks = P->dense_chunks;
+    return SPG_OK;
+}
+
+extern "C" spg_status spg_profile_read(spg_plan P, spg_kernel_time* out, int32_t cap, int32_t* n) {
+    if (!P || !n) return fail(SPG_ERR_ARG, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    for (auto& r : P->prof_pending) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.beg, r.end);
+        auto it = std::find_if(P->prof_acc.begin(), P->prof_acc.end(),
+                               [&](const spg_kernel_time& k) { return r.name == k.name; });
+        if (it == P->prof_acc.end()) {
+            spg_kernel_time k;
+            std::memset(&k, 0, sizeof(k));
+            std::snprintf(k.name, sizeof(k.name), "%s", r.name.c_str());
+            P->prof_acc.push_back(k);
+            it = P->prof_acc.end() - 1;
+        }
+        it->launches += 1;
+        it->total_ms += ms;
+        P->event_pool.push_back(r.beg);
+        P->event_pool.push_back(r.end);
+    }
+    P->prof_pending.clear();
+    int32_t k = 0;
+    for (auto& r : P->prof_acc) {
+        if (out && k < cap) out[k] = r;
+        ++k;
+    }
+    *n = k;
+    return SPG_OK;
+}
+
+extern "C" spg_status spg_profile_reset(spg_plan P) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    for (auto& r : P->prof_pending) {
+        P->event_pool.push_back(r.beg);
+        P->event_pool.push_back(r.end);
+    }
+    P->prof_pending.clear();
+    P->prof_acc.clear();
+    return SPG_OK;
+}

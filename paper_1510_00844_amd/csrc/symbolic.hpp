@@ -1,0 +1,130 @@
+// Symbolic phase: nnz(C(i,:)) = |union over stored A(i,k), k in window, of
+// the column sets of B(k,:)|, the stored-set part of the product definition
+// (Section 2; explicit zeros count, so values are never read).  Each bin of
+// rows gets its own accumulator:
+//   SMALL  (<= 64 products): one wave per row, the products' column keys
+//          sit one per lane and are sorted across the wave; the count is
+//          the number of run heads.
+//   HASH   : workgroup per row, open-addressing table of int32 keys in LDS
+//            (linear probing, >= 2 slots per product).
+//   DENSE  : workgroup per row, an n-bit bitmap in LDS (n <= 2^19), the
+//            structural part of the sparse accumulator of Section 3.
+#pragma once
+#include "products.hpp"
+
+namespace spg {
+
+constexpr int32_t EMPTY_KEY = -1;
+
+// Locate, for each lane, the product with flat index = lane among the row's
+// products (<= 64 of them): returns the A index p and B index q.  The A row
+// is walked in order, so flat order is ascending k, then ascending column.
+__device__ inline bool wave_locate_product(const Csr& A, const Csr& B, int64_t beg, int64_t end,
+                                           int64_t& p_out, int64_t& q_out) {
+    const int lane = lane_id();
+    int pos = 0;
+    bool have = false;
+    for (int64_t p = beg; p < end && pos < SPG_WAVE; ++p) {
+        int64_t k = A.col[p];
+        int64_t bs = B.rp[k];
+        int len = (int)(B.rp[k + 1] - bs);
+        if (lane >= pos && lane < pos + len) {
+            p_out = p;
+            q_out = bs + (lane - pos);
+            have = true;
+        }
+        pos += len;
+    }
+    return have;
+}
+
+// 4 waves per block, one row per wave.
+__global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
+                                                   const int64_t* a_beg, const int64_t* a_end,
+                                                   int64_t* cnt) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;  // whole wave leaves; no block barriers below
+    const int64_t i = rows[r];
+    int64_t p = 0, q = 0;
+    bool have = wave_locate_product(A, B, a_beg[i], a_end[i], p, q);
+    uint64_t key = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
+    key = wave_bitonic_sort_u64(key);
+    uint64_t prev = __shfl_up(key, 1, SPG_WAVE);
+    const int lane = lane_id();
+    bool head = key != ~0ull && (lane == 0 || prev != key);
+    uint64_t heads = __ballot(head);
+    if (lane == 0) cnt[i] = __popcll(heads);
+}
+
+template <int NT, int LOG2T>
+__global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* rows,
+                                                 const int64_t* a_beg, const int64_t* a_end,
+                                                 int64_t* cnt) {
+    constexpr int T = 1 << LOG2T;
+    __shared__ int32_t tab[T];
+    __shared__ ProductLds<NT> L;
+    __shared__ int32_t red[NT / SPG_WAVE + 1];
+    const int64_t i = rows[blockIdx.x];
+    for (int t = threadIdx.x; t < T; t += NT) tab[t] = EMPTY_KEY;
+    __syncthreads();
+    int32_t mine = 0;
+    for_each_product<NT>(
+        a_beg[i], a_end[i], L,
+        [&](int64_t p, int64_t& bs, int32_t& len) {
+            int64_t k = A.col[p];
+            bs = B.rp[k];
+            len = (int32_t)(B.rp[k + 1] - bs);
+        },
+        [&](int, int64_t) {},
+        [&](int, int64_t, int64_t q) {
+            const int32_t j = B.col[q];
+            uint32_t h = hash_slot(j, LOG2T);
+            while (true) {
+                int32_t cur = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cur == j) break;
+                if (cur == EMPTY_KEY) {
+                    int32_t old = atomicCAS(&tab[h], EMPTY_KEY, j);
+                    if (old == EMPTY_KEY) {
+                        ++mine;
+                        break;
+                    }
+                    if (old == j) break;
+                }
+                h = (h + 1) & (T - 1);
+            }
+        });
+    int32_t total = block_reduce_add<NT, int32_t>(mine, red);
+    if (threadIdx.x == 0) cnt[i] = total;
+}
+
+// Dynamic LDS: `nwords` 32-bit bitmap words covering columns [0, n).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* rows,
+                                                   const int64_t* a_beg, const int64_t* a_end,
+                                                   int64_t* cnt, int32_t nwords) {
+    extern __shared__ uint32_t bm[];
+    __shared__ ProductLds<NT> L;
+    __shared__ int32_t red[NT / SPG_WAVE + 1];
+    const int64_t i = rows[blockIdx.x];
+    for (int t = threadIdx.x; t < nwords; t += NT) bm[t] = 0u;
+    __syncthreads();
+    int32_t mine = 0;
+    for_each_product<NT>(
+        a_beg[i], a_end[i], L,
+        [&](int64_t p, int64_t& bs, int32_t& len) {
+            int64_t k = A.col[p];
+            bs = B.rp[k];
+            len = (int32_t)(B.rp[k + 1] - bs);
+        },
+        [&](int, int64_t) {},
+        [&](int, int64_t, int64_t q) {
+            const uint32_t j = (uint32_t)B.col[q];
+            const uint32_t bit = 1u << (j & 31);
+            uint32_t old = atomicOr(&bm[j >> 5], bit);
+            mine += (old & bit) ? 0 : 1;
+        });
+    int32_t total = block_reduce_add<NT, int32_t>(mine, red);
+    if (threadIdx.x == 0) cnt[i] = total;
+}
+
+}  // namespace spg

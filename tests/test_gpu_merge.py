@@ -1,0 +1,117 @@
+"""GPU parity of the layered product and the k-way layer merge (Section 4.4
+split of the inner dimension into c contiguous layers; Section 4.3 merge)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1510_00844_amd as spg
+import synth
+from gpu_util import check_rows_vs_oracle, rows_of, sample_rows, to_dev, to_host
+from synth import CSR
+from util import assert_same_structure, assert_values
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def plan():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p = spg.Plan()
+    yield p
+    p.close()
+
+
+def layered(plan, sr, A, B, c):
+    dA, dB = to_dev(A, sr), to_dev(B, sr)
+    layers = [spg.spgemm(plan, sr, dA, dB, lo, hi) for lo, hi in synth.layer_bounds(A.ncols, c)]
+    return layers, spg.spgemm_merge_layers(plan, sr, layers), spg.spgemm(plan, sr, dA, dB)
+
+
+@pytest.mark.parametrize("c", [1, 2, 4, 16])
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_layers_merge_small(plan, c, sr):
+    A = synth.rmat(12, 16, synth.ER, seed=31)
+    B = synth.rmat(12, 16, synth.G500, seed=32)
+    if sr != "f64":
+        kind = "ones_i64" if sr == "i64" else "true_bool"
+        A, B = synth.with_values(A, kind), synth.with_values(B, kind)
+    layers, M, U = layered(plan, sr, A, B, c)
+    # every layer equals the oracle's windowed product
+    for (lo, hi), L in zip(synth.layer_bounds(A.ncols, c), layers):
+        got = to_host(L)
+        ref = oracle.spgemm(A, B, sr, lo, hi)
+        assert_same_structure(got, ref)
+        if sr == "f64":
+            s, t = oracle.f64_tolerance(A, B, ref, lo, hi)
+            assert_values(got, ref, sr, s, t)
+        else:
+            assert_values(got, ref, sr)
+    # merge of the device layers equals the oracle merge of the same layers
+    hl = [to_host(L) for L in layers]
+    ref_m = oracle.merge(hl, sr)
+    got_m = to_host(M)
+    assert_same_structure(got_m, ref_m)
+    if sr == "f64":
+        assert np.allclose(got_m.val, ref_m.val, rtol=1e-13, atol=0)
+    else:
+        assert_values(got_m, ref_m, sr)
+    # and the layered result equals the unsplit product
+    U_h = to_host(U)
+    assert_same_structure(got_m, U_h)
+    if sr != "f64":
+        assert np.array_equal(got_m.val, U_h.val)
+    else:
+        s, t = oracle.f64_tolerance(A, B, U_h)
+        assert_values(got_m, U_h, sr, s, t)
+
+
+@pytest.mark.parametrize("c", [4, 16])
+def test_c3_er_s18_layers(plan, c):
+    """C3: ER scale 18, edge factor 16, A and B independent, c layers."""
+    A = synth.rmat(18, 16, synth.ER, seed=3)
+    B = synth.rmat(18, 16, synth.ER, seed=4)
+    print("case C3 c=%d" % c, flush=True)
+    layers, M, U = layered(plan, "f64", A, B, c)
+    assert torch.equal(M.row_ptr, U.row_ptr) and torch.equal(M.col, U.col)
+    tot = sum(L.nnz for L in layers)
+    f = int(oracle.row_flops(A, B).sum())
+    assert U.nnz <= tot <= f
+    rows = sample_rows(A, B, 1000, seed=5)
+    check_rows_vs_oracle(M, A, B, "f64", rows)
+    for (lo, hi), L in list(zip(synth.layer_bounds(A.ncols, c), layers))[:2]:
+        check_rows_vs_oracle(L, A, B, "f64", rows[:200], lo, hi)
+
+
+def _layer(m, n, rows_lens, seed, sr="f64"):
+    rng = np.random.default_rng(seed)
+    rr, cc = [], []
+    for i, L in enumerate(rows_lens):
+        cs = rng.choice(n, min(L, n), replace=False)
+        rr += [i] * len(cs)
+        cc += cs.tolist()
+    vals = {"f64": rng.random(len(rr)), "i64": rng.integers(-5, 6, len(rr)),
+            "bool": (rng.random(len(rr)) < 0.7).astype(np.uint8)}[sr]
+    return synth.canonical_from_coo(m, n, rr, cc, vals, dup="first")
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_merge_edge_cases(plan, sr):
+    """Empty layers, c = 1, rows in every merge bin (<= 64 entries in all
+    layers, <= 4096, and longer ones taking the chunked dense path)."""
+    n = 20000
+    lens = [0, 1, 5, 30, 64, 65, 300, 1500, 3000, 5000, 9000, 19000]
+    layers_h = [_layer(len(lens), n, lens, 10 + l, sr) for l in range(3)]
+    layers_h.append(_layer(len(lens), n, [0] * len(lens), 99, sr))  # an empty layer
+    for sel in ([0], [3], [0, 1], [0, 1, 2, 3]):
+        hl = [layers_h[x] for x in sel]
+        M = spg.spgemm_merge_layers(plan, sr, [to_dev(L, sr) for L in hl])
+        ref = oracle.merge(hl, sr)
+        got = to_host(M)
+        assert_same_structure(got, ref)
+        if sr == "f64":
+            assert np.allclose(got.val, ref.val, rtol=1e-13, atol=0)
+        else:
+            assert_values(got, ref, sr)

@@ -1,0 +1,260 @@
+"""GPU parity of the HIP SpGEMM path (through the C ABI) against the oracle.
+
+Structure and INT64/boolean values are compared exactly; FP64 values to
+1e-12 relative per entry, or within the summation-order bound for entries
+with many terms (tests/util.py).  Full-size configurations compare sampled
+rows (heaviest, lightest and random ones) plus properties of the whole
+result that hold at any size.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1510_00844_amd as spg
+import synth
+from gpu_util import check_full_vs_oracle, check_rows_vs_oracle, rows_of, sample_rows, to_dev, to_host
+from synth import CSR
+from util import assert_same_structure, assert_values
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def plan():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p = spg.Plan()
+    yield p
+    p.close()
+
+
+def run(plan, sr, A, B, k_lo=None, k_hi=None):
+    return spg.spgemm(plan, sr, to_dev(A, sr), to_dev(B, sr), k_lo, k_hi)
+
+
+def with_kind(M, sr, seed=0):
+    kind = {"f64": "uniform_f64", "i64": "ones_i64", "bool": "true_bool"}[sr]
+    return synth.with_values(M, kind, seed=seed)
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_c1_er_uniform_full(plan, sr):
+    print("case C1 ER-uniform n=4096 sr=%s" % sr, flush=True)
+    A = synth.er_uniform_columns(4096, 4, seed=1)
+    A = A if sr == "f64" else with_kind(A, sr)
+    C = run(plan, sr, A, A)
+    check_full_vs_oracle(C, A, A, sr)
+    st = plan.stats()
+    assert st["flops"] == 65536
+
+
+def _binned_matrices(seed=7):
+    """A (m x K) whose rows cover every accumulator bin against an R-MAT B
+    with hub rows: empty rows, one-entry rows, a few products, each hash
+    size, and rows whose products exceed the hash limit."""
+    B = synth.rmat(13, 16, synth.G500, seed=seed)
+    K = B.nrows
+    rng = np.random.default_rng(seed)
+    blen = np.diff(B.row_ptr)
+    order = np.argsort(-blen)
+    rows, cols = [], []
+    r = 0
+    targets = [0, 1, 1, 2, 3, 5, 8, 12, 20, 40, 60, 100, 200, 400, 800, 1500, 3000, 6000, 12000, 30000, 60000]
+    for rep in range(6):
+        for tf in targets:
+            if tf == 0:
+                r += 1
+                continue
+            if tf == 1:
+                k = int(rng.integers(0, K))
+                rows.append(r); cols.append(k)
+                r += 1
+                continue
+            picked, f = set(), 0
+            pool = order if tf > 2000 else rng.permutation(K)
+            for k in pool:
+                k = int(k)
+                if k in picked or blen[k] == 0:
+                    continue
+                if f + blen[k] > tf and f > 0:
+                    continue
+                picked.add(k)
+                f += int(blen[k])
+                if f >= tf * 0.9:
+                    break
+            for k in picked:
+                rows.append(r); cols.append(k)
+            r += 1
+    # rows whose products collide heavily: B rows K..K+59 share the same 12
+    # columns, so 8 of them give 96 products but only 12 outputs
+    extra = 60
+    shared = rng.choice(B.ncols, 12, replace=False)
+    brow = np.repeat(np.arange(K, K + extra), 12)
+    bcol = np.tile(shared, extra)
+    B_rows = np.repeat(np.arange(K), np.diff(B.row_ptr))
+    B = synth.canonical_from_coo(K + extra, B.ncols, np.concatenate([B_rows, brow]),
+                                 np.concatenate([B.col.astype(np.int64), bcol]),
+                                 np.concatenate([B.val, rng.random(brow.size)]), dup="first")
+    for rep in range(20):
+        ks = rng.choice(extra, 8, replace=False) + K
+        rows += [r] * 8
+        cols += ks.tolist()
+        r += 1
+    A = synth.canonical_from_coo(r, K + extra, rows, cols, rng.random(len(rows)), dup="first")
+    return A, B
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_every_bin_full(plan, sr):
+    A, B = _binned_matrices()
+    print("case bins m=%d sr=%s" % (A.nrows, sr), flush=True)
+    A, B = (A, B) if sr == "f64" else (with_kind(A, sr), with_kind(B, sr))
+    C = run(plan, sr, A, B)
+    st = plan.stats()
+    used_sym = [b for b in range(spg.NBINS) if st["sym_rows"][b]]
+    used_num = [b for b in range(spg.NBINS) if st["num_rows"][b]]
+    for b in (0, 1, 2, 3, 4, 5, 6, 7, 8, 12):
+        assert b in used_sym or b in used_num, "bin %s not exercised" % spg.BIN_NAMES[b]
+    assert 12 in used_num and 12 in used_sym
+    check_full_vs_oracle(C, A, B, sr)
+
+
+def test_small_rows_exact_order(plan):
+    """Rows with <= 64 products fold equal columns in ascending k, the
+    oracle's order, so FP64 matches bit for bit there."""
+    A = synth.random_csr(300, 200, 0.02, seed=41, kind="f64")
+    B = synth.random_csr(200, 150, 0.03, seed=42, kind="f64")
+    f = oracle.row_flops(A, B)
+    assert f.max() <= 64
+    C = to_host(run(plan, "f64", A, B))
+    ref = oracle.spgemm(A, B, "f64")
+    assert_same_structure(C, ref)
+    assert C.val.tobytes() == ref.val.tobytes()
+
+
+@pytest.mark.parametrize("window", [(0, 0), (0, 1), (100, 1000), (4000, 8192), (8191, 8192), (0, 8192)])
+def test_inner_windows(plan, window):
+    A = synth.rmat(13, 16, synth.G500, seed=43)
+    B = synth.rmat(13, 16, synth.ER, seed=44)
+    lo, hi = window
+    print("case window %s" % (window,), flush=True)
+    C = run(plan, "f64", A, B, lo, hi)
+    check_full_vs_oracle(C, A, B, "f64", lo, hi)
+
+
+def test_degenerate_shapes(plan):
+    cases = [
+        (synth.random_csr(0, 5, 0.5, 1), synth.random_csr(5, 4, 0.5, 2)),
+        (synth.random_csr(4, 0, 0.5, 1), synth.random_csr(0, 4, 0.5, 2)),
+        (synth.random_csr(4, 5, 0.5, 1), synth.random_csr(5, 0, 0.5, 2)),
+        (synth.random_csr(7, 6, 0.0, 1), synth.random_csr(6, 3, 0.5, 2)),
+        (synth.random_csr(7, 6, 1.0, 1), synth.random_csr(6, 3, 1.0, 2)),
+    ]
+    for A, B in cases:
+        print("case degenerate %dx%d * %dx%d" % (A.nrows, A.ncols, B.nrows, B.ncols), flush=True)
+        C = run(plan, "f64", A, B)
+        ref = oracle.spgemm(A, B, "f64")
+        got = to_host(C)
+        assert_same_structure(got, ref)
+        assert_values(got, ref, "f64")
+
+
+def test_all_products_in_one_column(plan):
+    """Every product lands in column 0: one output per row with up to
+    thousands of terms (hash and dense paths under maximal collision)."""
+    K = 5000
+    B = synth.canonical_from_coo(K, 3, np.arange(K), np.zeros(K, np.int64), np.ones(K), dup="first")
+    rng = np.random.default_rng(3)
+    rows, cols = [], []
+    for r, nz in enumerate([1, 2, 30, 64, 65, 500, 2000, 4999, 5000]):
+        ks = rng.choice(K, nz, replace=False)
+        rows += [r] * nz
+        cols += ks.tolist()
+    A = synth.canonical_from_coo(9, K, rows, cols, rng.integers(1, 5, len(rows)).astype(np.float64))
+    for sr in ("f64", "i64", "bool"):
+        AA = A if sr == "f64" else synth.CSR(A.nrows, A.ncols, A.row_ptr, A.col,
+                                             A.val.astype(np.int64) if sr == "i64" else np.ones(A.nnz, np.uint8))
+        BB = B if sr == "f64" else with_kind(B, sr)
+        check_full_vs_oracle(run(plan, sr, AA, BB), AA, BB, sr)
+
+
+def test_dense_operands(plan):
+    """Fully dense small operands: every row is heavy; output rows are dense."""
+    A = synth.random_csr(40, 300, 1.0, 5, "f64")
+    B = synth.random_csr(300, 9000, 1.0, 6, "f64")
+    check_full_vs_oracle(run(plan, "f64", A, B), A, B, "f64")
+
+
+def test_rmat_s16_c2(plan):
+    """C2: R-MAT G500 scale 16, edge factor 16, FP64 U(0,1): full row
+    pointers exact, sampled rows vs the oracle; INT64 all-ones sums to flops
+    and has the same structure; boolean values all true."""
+    A = synth.rmat(16, 16, synth.G500, seed=2)
+    print("case C2 f64 nnz(A)=%d" % A.nnz, flush=True)
+    C = run(plan, "f64", A, A)
+    st = plan.stats()
+    f = oracle.row_flops(A, A)
+    assert st["flops"] == int(f.sum())
+    ref_counts = np.diff(oracle.spgemm(A, A, "bool", values=False).row_ptr)
+    assert np.array_equal(np.diff(C.row_ptr.cpu().numpy()), ref_counts)
+    rows = sample_rows(A, A, 1200, seed=1)
+    over = check_rows_vs_oracle(C, A, A, "f64", rows)
+    print("C2 f64 entries needing the order bound: %d" % over, flush=True)
+    A1 = with_kind(A, "i64")
+    Ci = run(plan, "i64", A1, A1)
+    assert torch.equal(Ci.row_ptr, C.row_ptr) and torch.equal(Ci.col, C.col)
+    assert int(Ci.val.sum().item()) == int(f.sum())
+    check_rows_vs_oracle(Ci, A1, A1, "i64", rows)
+    Ab = with_kind(A, "bool")
+    Cb = run(plan, "bool", Ab, Ab)
+    assert torch.equal(Cb.row_ptr, C.row_ptr) and torch.equal(Cb.col, C.col)
+    assert bool((Cb.val == 1).all().item())
+
+
+def test_determinism_integer(plan):
+    A = synth.with_values(synth.rmat(14, 16, synth.G500, seed=12), "ones_i64")
+    C1 = run(plan, "i64", A, A)
+    C2 = run(plan, "i64", A, A)
+    assert torch.equal(C1.row_ptr, C2.row_ptr) and torch.equal(C1.col, C2.col) and torch.equal(C1.val, C2.val)
+
+
+def test_errors(plan):
+    A = to_dev(synth.random_csr(5, 6, 0.5, 1))
+    B = to_dev(synth.random_csr(7, 3, 0.5, 2))
+    with pytest.raises(spg.SpgError) as e:
+        spg.spgemm_symbolic(plan, "f64", A, B)
+    assert e.value.name == "SPG_ERR_SHAPE"
+    B2 = to_dev(synth.random_csr(6, 3, 0.5, 2))
+    with pytest.raises(spg.SpgError) as e:
+        spg.spgemm_symbolic(plan, "f64", A, B2, 3, 2)
+    assert e.value.name == "SPG_ERR_ARG"
+    with pytest.raises(spg.SpgError) as e:
+        spg.spgemm_symbolic(plan, "f64", A, B2, 0, 7)
+    assert e.value.name == "SPG_ERR_ARG"
+    rp, nnz = spg.spgemm_symbolic(plan, "f64", A, B2)
+    other = to_dev(synth.random_csr(5, 6, 0.5, 9))
+    with pytest.raises(spg.SpgError) as e:
+        spg.spgemm_numeric(plan, "f64", other, B2, rp, nnz)
+    assert e.value.name == "SPG_ERR_STATE"
+    vplan = spg.Plan(validate=True)
+    bad = spg.DeviceCSR.from_arrays(2, 4, [0, 2, 3], [3, 1, 0], np.ones(3))
+    with pytest.raises(spg.SpgError) as e:
+        spg.spgemm_symbolic(vplan, "f64", bad, to_dev(synth.random_csr(4, 2, 0.5, 3)))
+    assert e.value.name == "SPG_ERR_NOT_CANONICAL"
+    vplan.close()
+
+
+def test_rmat_s19_c5_sampled(plan):
+    """C5 shape (R-MAT G500 scale 19): sampled rows, including the hub rows
+    with millions of products, against the oracle."""
+    A = synth.rmat(19, 16, synth.G500, seed=6)
+    print("case C5 nnz(A)=%d" % A.nnz, flush=True)
+    C = run(plan, "f64", A, A)
+    st = plan.stats()
+    assert st["flops"] == int(oracle.row_flops(A, A).sum())
+    rows = sample_rows(A, A, 400, seed=2)
+    check_rows_vs_oracle(C, A, A, "f64", rows)
+    del C
+    torch.cuda.empty_cache()
