@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
+    ap.add_argument("--dense-cols", type=int, default=0, help="columns per dense accumulator chunk")
     return ap.parse_args()
 
 
@@ -50,13 +51,16 @@ def kernel_bytes(name: str, st: dict, sr: str) -> float:
     C entries written; w = value bytes)."""
     import paper_1510_00844_amd as spg
     w = value_width(sr)
-    bins = {"tiny": [1], "small": [2], "dense": [12], "bitmap": [12]}
+    bins = {"tiny": [1], "small": [2], "dense": [12], "bitmap": [12], "dense_par": [11]}
     kind, _, tail = name.partition("_")
     b = None
     if tail.startswith("hash"):
         T = int(tail[4:])
         b = 3 + (T.bit_length() - 1 - 7)
         idx = [b]
+    elif tail.startswith("rank"):
+        cap = int(tail[4:])
+        idx = [13 + (cap.bit_length() - 1 - 12)]
     else:
         idx = bins.get(tail)
         if idx is None:
@@ -100,7 +104,7 @@ def main():
     A = synth.rmat(args.scale, 16, synth.G500, seed=2)
     sr = "f64"
     dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
-    plan = spg.Plan(profile=not args.no_profile)
+    plan = spg.Plan(profile=not args.no_profile, dense_chunk_cols=args.dense_cols)
 
     def step():
         rp, nnz = spg.spgemm_symbolic(plan, sr, dA, dA)

@@ -126,8 +126,10 @@ enum {
     SPG_BIN_TINY = 1,   /* one stored A entry in the window: output = scaled B row */
     SPG_BIN_SMALL = 2,  /* few products: one wave, keys in registers */
     SPG_BIN_HASH0 = 3,  /* LDS hash table bins, 128 << (b - SPG_BIN_HASH0) slots */
-    SPG_BIN_DENSE = 12, /* large rows: LDS bitmap / dense chunked accumulator */
-    SPG_NBINS = 13
+    SPG_BIN_DENSE_PAR = 11, /* numeric only: column chunks of one row in parallel workgroups */
+    SPG_BIN_DENSE = 12, /* large rows: LDS bitmap (symbolic) / column-chunked dense accumulator (numeric) */
+    SPG_BIN_RANK0 = 13, /* numeric only: rank-space accumulator of 4096 << (b - SPG_BIN_RANK0) values */
+    SPG_NBINS = 16
 };
 
 /* Statistics of the last symbolic (and numeric) call, read back on demand

@@ -22,8 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libspgemm.so")
 SEMIRINGS = {"f64": 0, "i64": 1, "bool": 2}
 TORCH_DTYPE = {"f64": torch.float64, "i64": torch.int64, "bool": torch.uint8}
 
-NBINS = 13
-BIN_NAMES = ["empty", "tiny", "small"] + ["hash%d" % (128 << b) for b in range(9)] + ["dense"]
+NBINS = 16
+BIN_NAMES = (["empty", "tiny", "small"] + ["hash%d" % (128 << b) for b in range(8)] + ["dense_par", "dense"]
+             + ["rank%d" % (4096 << b) for b in range(3)])
 
 
 class SpgError(RuntimeError):

@@ -144,6 +144,33 @@ __device__ inline T block_exclusive_scan(T v, T* total, T* tmp) {
     return res;
 }
 
+// Workgroup min and max of one value per thread (tmp: 2*(NT/64) elements).
+template <int NT, typename T>
+__device__ inline void block_min_max(T& mn, T& mx, T* tmp) {
+    constexpr int NW = NT / SPG_WAVE;
+#pragma unroll
+    for (int d = SPG_WAVE / 2; d > 0; d >>= 1) {
+        T a = __shfl_xor(mn, d, SPG_WAVE);
+        T b = __shfl_xor(mx, d, SPG_WAVE);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if (NW == 1) return;
+    const int wid = threadIdx.x / SPG_WAVE;
+    if (lane_id() == 0) {
+        tmp[wid] = mn;
+        tmp[NW + wid] = mx;
+    }
+    __syncthreads();
+    mn = tmp[0];
+    mx = tmp[NW];
+    for (int w = 1; w < NW; ++w) {
+        mn = tmp[w] < mn ? tmp[w] : mn;
+        mx = tmp[NW + w] > mx ? tmp[NW + w] : mx;
+    }
+    __syncthreads();
+}
+
 template <int NT, typename T>
 __device__ inline T block_reduce_add(T v, T* tmp) {
     T total;

@@ -8,6 +8,11 @@
 //   HASH   workgroup per row: LDS open-addressing table sized >= 2 slots per
 //          output, semiring add by LDS atomics, then compaction and an LDS
 //          bitonic sort by column
+//   RANK   rows whose symbolic pass kept an n-bit bitmap: the bitmap is
+//          reloaded, each word gets the count of set bits before it, c_col is
+//          written straight from the bitmap, and values accumulate in LDS at
+//          index rank(j) = set bits below column j, i.e. directly in output
+//          order (a sparse accumulator compressed to the row's own columns)
 //   DENSE  workgroup per row sweeping column chunks of W: an LDS dense
 //          accumulator plus occupancy bitmap per chunk (the sparse
 //          accumulator of Section 3, blocked by columns so it fits LDS);
@@ -17,6 +22,12 @@
 #include "symbolic.hpp"
 
 namespace spg {
+
+template <typename V>
+struct BEntry {
+    int32_t col;
+    V val;
+};
 
 // One wave per row, rows given by a list.
 template <int SR>
@@ -94,23 +105,26 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     __shared__ V tval[T];
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
+    __shared__ int32_t mm[2 * (NT / SPG_WAVE)];
+    __shared__ V s_av[NT];
     const int64_t i = rows[blockIdx.x];
     for (int t = threadIdx.x; t < T; t += NT) {
         tkey[t] = EMPTY_KEY;
         tval[t] = S::zero();
     }
     __syncthreads();
-    for_each_product<NT>(
+    for_each_product_u<NT, 4>(
         a_beg[i], a_end[i], L,
         [&](int64_t p, int64_t& bs, int32_t& len) {
             int64_t k = A.col[p];
             bs = B.rp[k];
             len = (int32_t)(B.rp[k + 1] - bs);
         },
-        [&](int, int64_t) {},
-        [&](int, int64_t p, int64_t q) {
-            const int32_t j = B.col[q];
-            const V v = S::mul(S::load(A.val, p), S::load(B.val, q));
+        [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
+        [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
+        [&](int t, const BEntry<V>& x) {
+            const int32_t j = x.col;
+            const V v = S::mul(s_av[t], x.val);
             uint32_t h = hash_slot(j, LOG2T);
             // the table has >= 2 slots per output of the symbolic count, so a
             // probe ends within T steps; the cap only guards inputs that
@@ -143,6 +157,57 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     int32_t pos = block_exclusive_scan<NT, int32_t>(mine, &cnt, red);
     const int64_t o = c_rp[i];
     const int32_t cnt_sym = (int32_t)(c_rp[i + 1] - o);
+    // Output order.  When the row's columns span few enough bitmap words, the
+    // rank of a column is the popcount of the bitmap below it (prefix of
+    // per-word popcounts): no sort.  Otherwise sort (column, slot) keys.
+    int32_t kmin = 0x7fffffff, kmax = -1;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        if (rk[s] != EMPTY_KEY) {
+            kmin = rk[s] < kmin ? rk[s] : kmin;
+            kmax = rk[s] > kmax ? rk[s] : kmax;
+        }
+    }
+    block_min_max<NT, int32_t>(kmin, kmax, mm);
+    const int32_t nw = kmax >= kmin ? ((kmax - kmin) >> 5) + 1 : 0;
+    if (nw > 0 && nw <= T && nw <= 8 * cnt + 64) {
+        uint32_t* bm = reinterpret_cast<uint32_t*>(tkey);
+        int32_t* wp = reinterpret_cast<int32_t*>(tval);
+        for (int w = threadIdx.x; w < nw; w += NT) bm[w] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            if (rk[s] != EMPTY_KEY) {
+                const int32_t j = rk[s] - kmin;
+                atomicOr(&bm[j >> 5], 1u << (j & 31));
+            }
+        }
+        __syncthreads();
+        const int wpt = (nw + NT - 1) / NT;
+        const int w0 = threadIdx.x * wpt;
+        int32_t part = 0;
+        for (int w = w0; w < w0 + wpt && w < nw; ++w) part += __popc(bm[w]);
+        int32_t dummy;
+        int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
+        for (int w = w0; w < w0 + wpt && w < nw; ++w) {
+            wp[w] = run;
+            run += __popc(bm[w]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            if (rk[s] != EMPTY_KEY) {
+                const int32_t j = rk[s] - kmin;
+                const int32_t w = j >> 5;
+                const int32_t rank = wp[w] + __popc(bm[w] & ((1u << (j & 31)) - 1u));
+                if (rank < cnt_sym) {
+                    c_col[o + rank] = rk[s];
+                    if (c_val) S::store(c_val, o + rank, rv[s]);
+                }
+            }
+        }
+        return;
+    }
     if (cnt > T / 2) cnt = T / 2;  // sort buffer capacity; only reached if inputs changed
     // reuse the table: compacted values in tkey's bytes, sort keys in tval's
     V* cval = reinterpret_cast<V*>(tkey);
@@ -184,87 +249,168 @@ __global__ void __launch_bounds__(256) k_split_table(Csr B, int32_t W, int32_t P
     split[idx] = (int32_t)(r - rs);
 }
 
-template <int SR, int NT, int W>
+// PAR = false: one workgroup per row sweeps the P chunks in order.
+// PAR = true: one workgroup per (row, chunk); the chunk's output offset is
+// the row offset plus the counts of the earlier chunks recorded by the
+// symbolic bitmap pass (chunk_cnt, slot heavy_idx[i]), so chunks of one
+// row run side by side and the largest rows do not serialize the kernel.
+template <int SR, int NT, int W, bool PAR>
 __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* rows,
                                                   const int64_t* a_beg, const int64_t* a_end,
                                                   const int32_t* split, int32_t P,
+                                                  const int32_t* chunk_cnt, const int32_t* heavy_idx,
                                                   const int64_t* c_rp, int32_t* c_col, void* c_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
     constexpr int NWD = W / 32;
+    static_assert(NWD <= NT, "one bitmap word per thread at most");
     __shared__ V acc[W];
     __shared__ uint32_t bits[NWD];
-    __shared__ int32_t wpre[NWD];
     __shared__ V s_av[NT];
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
-    const int64_t i = rows[blockIdx.x];
+    const int64_t i = rows[PAR ? blockIdx.x / P : blockIdx.x];
     const int64_t beg = a_beg[i], end = a_end[i];
     int64_t off = c_rp[i];
     const int64_t row_end = c_rp[i + 1];
-    for (int c = 0; c < P; ++c) {
-        for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
-        for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
-        __syncthreads();
+    int c_first = 0, c_last = P;
+    if (PAR) {
+        c_first = blockIdx.x % P;
+        c_last = c_first + 1;
+        const int32_t* cc = chunk_cnt + (int64_t)heavy_idx[i] * P;
+        for (int c = 0; c < c_first; ++c) off += cc[c];
+    }
+    // the accumulator is cleared once; emission resets exactly the slots it
+    // reads, so later chunks start from zero again
+    for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
+    for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
+    // Rows with at most NT entries in the window keep their A entry (column
+    // k, start of B(k,:), position reached in B(k,:)) in registers across
+    // the chunks, so each chunk costs one split-table load per entry.
+    const bool single = !PAR && end - beg <= NT;
+    int64_t my_k = 0, my_rs = 0;
+    int32_t my_cur = 0;
+    if (single && beg + (int64_t)threadIdx.x < end) {
+        const int64_t p = beg + threadIdx.x;
+        my_k = A.col[p];
+        my_rs = B.rp[my_k];
+        s_av[threadIdx.x] = S::load(A.val, p);
+    }
+    __syncthreads();
+    for (int c = c_first; c < c_last; ++c) {
         const int32_t cbase = c * W;
-        for_each_product<NT>(
+        for_each_product_u<NT, 4>(
             beg, end, L,
             [&](int64_t p, int64_t& bs, int32_t& len) {
-                int64_t k = A.col[p];
-                int64_t rs = B.rp[k];
-                if (P > 1) {
-                    const int32_t* sp = split + k * (P + 1) + c;
-                    bs = rs + sp[0];
-                    len = sp[1] - sp[0];
+                if (single) {
+                    const int32_t nxt = P > 1 ? split[my_k * (P + 1) + c + 1] : (int32_t)(B.rp[my_k + 1] - my_rs);
+                    bs = my_rs + my_cur;
+                    len = nxt - my_cur;
+                    my_cur = nxt;
                 } else {
-                    bs = rs;
-                    len = (int32_t)(B.rp[k + 1] - rs);
-                }
-            },
-            [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
-            [&](int t, int64_t, int64_t q) {
-                const int32_t j = B.col[q] - cbase;
-                S::lds_add(&acc[j], S::mul(s_av[t], S::load(B.val, q)));
-                atomicOr(&bits[j >> 5], 1u << (j & 31));
-            });
-        // exclusive prefix of per-word popcounts
-        int32_t chunk_total = 0;
-        {
-            // NWD <= 4*NT: each thread sums up to 4 consecutive words
-            constexpr int WPT = (NWD + NT - 1) / NT;
-            int32_t wc[WPT];
-            int32_t s = 0;
-#pragma unroll
-            for (int x = 0; x < WPT; ++x) {
-                int w = threadIdx.x * WPT + x;
-                wc[x] = w < NWD ? __popc(bits[w]) : 0;
-                s += wc[x];
-            }
-            int32_t pre = block_exclusive_scan<NT, int32_t>(s, &chunk_total, red);
-#pragma unroll
-            for (int x = 0; x < WPT; ++x) {
-                int w = threadIdx.x * WPT + x;
-                if (w < NWD) wpre[w] = pre;
-                pre += wc[x];
-            }
-        }
-        __syncthreads();
-        if (chunk_total) {
-            for (int j = threadIdx.x; j < W; j += NT) {
-                const uint32_t wbits = bits[j >> 5];
-                const uint32_t b = 1u << (j & 31);
-                if (wbits & b) {
-                    const int64_t o = off + wpre[j >> 5] + __popc(wbits & (b - 1));
-                    if (o < row_end) {
-                        c_col[o] = cbase + j;
-                        if (c_val) S::store(c_val, o, acc[j]);
+                    const int64_t k = A.col[p];
+                    const int64_t rs = B.rp[k];
+                    if (P > 1) {
+                        const int32_t* sp = split + k * (P + 1) + c;
+                        bs = rs + sp[0];
+                        len = sp[1] - sp[0];
+                    } else {
+                        bs = rs;
+                        len = (int32_t)(B.rp[k + 1] - rs);
                     }
                 }
+            },
+            [&](int t, int64_t p) {
+                if (!single) s_av[t] = S::load(A.val, p);
+            },
+            [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
+            [&](int t, const BEntry<V>& x) {
+                const int32_t j = x.col - cbase;
+                S::lds_add(&acc[j], S::mul(s_av[t], x.val));
+                atomicOr(&bits[j >> 5], 1u << (j & 31));
+            });
+        // thread t owns bitmap word t: prefix of popcounts, then its set bits
+        const uint32_t wbits = threadIdx.x < NWD ? bits[threadIdx.x] : 0u;
+        int32_t chunk_total;
+        int32_t pre = block_exclusive_scan<NT, int32_t>(__popc(wbits), &chunk_total, red);
+        if (wbits) {
+            int64_t o = off + pre;
+            uint32_t wb = wbits;
+            while (wb) {
+                const int b = __ffs(wb) - 1;
+                wb &= wb - 1;
+                const int j = threadIdx.x * 32 + b;
+                if (o < row_end) {
+                    c_col[o] = cbase + j;
+                    if (c_val) S::store(c_val, o, acc[j]);
+                }
+                acc[j] = S::zero();
+                ++o;
             }
+            bits[threadIdx.x] = 0u;
         }
         off += chunk_total;
         __syncthreads();
     }
+}
+
+// Dynamic LDS: nwords 64-bit words (bits in the low half, count of set bits
+// in all earlier words in the high half), then `cap` accumulators.
+template <int SR, int NT>
+__global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* rows,
+                                                 const int64_t* a_beg, const int64_t* a_end,
+                                                 const uint32_t* bm_save, const int32_t* heavy_idx,
+                                                 int32_t nwords, const int64_t* c_rp, int32_t* c_col,
+                                                 void* c_val) {
+    typedef Sr<SR> S;
+    typedef typename S::acc_t V;
+    extern __shared__ uint64_t dyn[];
+    uint64_t* bw = dyn;
+    V* acc = reinterpret_cast<V*>(dyn + nwords);
+    __shared__ V s_av[NT];
+    __shared__ ProductLds<NT> L;
+    __shared__ int32_t red[NT / SPG_WAVE + 1];
+    const int64_t i = rows[blockIdx.x];
+    const int64_t off = c_rp[i];
+    const int32_t cnt = (int32_t)(c_rp[i + 1] - off);
+    const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords;
+    // each thread owns a contiguous run of words
+    const int wpt = (nwords + NT - 1) / NT;
+    const int w0 = threadIdx.x * wpt;
+    const int w1 = w0 + wpt < nwords ? w0 + wpt : nwords;
+    int32_t part = 0;
+    for (int w = w0; w < w1; ++w) part += __popc(src[w]);
+    int32_t dummy;
+    int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
+    for (int w = w0; w < w1; ++w) {
+        uint32_t bits = src[w];
+        bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (run < cnt) c_col[off + run] = w * 32 + b;
+            ++run;
+        }
+    }
+    for (int r = threadIdx.x; r < cnt; r += NT) acc[r] = S::zero();
+    __syncthreads();
+    for_each_product_u<NT, 4>(
+        a_beg[i], a_end[i], L,
+        [&](int64_t p, int64_t& bs, int32_t& len) {
+            int64_t k = A.col[p];
+            bs = B.rp[k];
+            len = (int32_t)(B.rp[k + 1] - bs);
+        },
+        [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
+        [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
+        [&](int t, const BEntry<V>& x) {
+            const uint32_t j = (uint32_t)x.col;
+            const uint64_t wd = bw[j >> 5];
+            const int32_t rank = (int32_t)(wd >> 32) + __popc((uint32_t)wd & ((1u << (j & 31)) - 1u));
+            if (rank < cnt) S::lds_add(&acc[rank], S::mul(s_av[t], x.val));
+        });
+    if (c_val)
+        for (int r = threadIdx.x; r < cnt; r += NT) S::store(c_val, off + r, acc[r]);
 }
 
 }  // namespace spg

@@ -2,12 +2,12 @@
 //
 // Row i of C gathers, for every stored A(i,k) in the window, the stored
 // entries of B(k,:) (the row form of Algorithm 1).  B rows differ wildly in
-// length (R-MAT hubs), so instead of giving each thread one A entry, a batch
-// of NT A entries is turned into a flat index space of products with a
-// workgroup prefix sum of their B-segment lengths; thread f then finds its
-// A entry by binary search over the NT offsets held in LDS.  Neighbouring
-// threads read neighbouring B entries, so gathers stay coalesced and no
-// thread walks a long B row alone.
+// length (R-MAT hubs), so a batch of NT A entries is turned into a flat index
+// space of products with a workgroup prefix sum of their B-segment lengths,
+// and every thread takes an equal contiguous range of that space (a merge
+// path over the segment offsets): one binary search over the NT offsets in
+// LDS finds its first segment, after which it walks forward.  No thread walks
+// a long B row alone and no product pays for a search.
 #pragma once
 #include "common.hpp"
 
@@ -41,14 +41,87 @@ __device__ inline void for_each_product(int64_t a_beg, int64_t a_end, ProductLds
         L.bstart[threadIdx.x] = bs;
         if (threadIdx.x == 0) L.off[NT] = total;
         __syncthreads();
-        for (int32_t f = threadIdx.x; f < total; f += NT) {
+        const int32_t per = (total + NT - 1) / NT;
+        int32_t f = (int32_t)threadIdx.x * per;
+        const int32_t fend = f + per < total ? f + per : total;
+        if (f < fend) {
             // largest t with off[t] <= f  (off[0] = 0 <= f < off[NT] = total)
-            int lo = 0, hi = NT;
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (L.off[mid] <= f) lo = mid; else hi = mid;
+            int t = 0, hi = NT;
+            while (hi - t > 1) {
+                int mid = (t + hi) >> 1;
+                if (L.off[mid] <= f) t = mid; else hi = mid;
             }
-            visit(lo, base + lo, L.bstart[lo] + (f - L.off[lo]));
+            int32_t seg_end = L.off[t + 1];
+            int64_t q = L.bstart[t] + (f - L.off[t]);
+            for (; f < fend; ++f, ++q) {
+                while (f >= seg_end) {  // next non-empty segment
+                    ++t;
+                    seg_end = L.off[t + 1];
+                    q = L.bstart[t];
+                }
+                visit(t, base + t, q);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Same enumeration, with the gathers of U consecutive products of a thread
+// issued back to back before any of them is applied: `load(q)` reads what
+// the product needs from B, `apply(t, x)` consumes it.  Keeping U loads in
+// flight per thread is what hides the gather latency.
+template <int NT, int U, class Seg, class Pre, class Load, class Apply>
+__device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
+                                          Pre pre, Load load, Apply apply) {
+    typedef decltype(load((int64_t)0)) X;
+    for (int64_t base = a_beg; base < a_end; base += NT) {
+        const int64_t p = base + threadIdx.x;
+        int64_t bs = 0;
+        int32_t len = 0;
+        if (p < a_end) {
+            seg(p, bs, len);
+            pre((int)threadIdx.x, p);
+        }
+        int32_t total;
+        int32_t off = block_exclusive_scan<NT, int32_t>(len, &total, L.tmp);
+        L.off[threadIdx.x] = off;
+        L.bstart[threadIdx.x] = bs;
+        if (threadIdx.x == 0) L.off[NT] = total;
+        __syncthreads();
+        const int32_t per = (total + NT - 1) / NT;
+        int32_t f = (int32_t)threadIdx.x * per;
+        const int32_t fend = f + per < total ? f + per : total;
+        if (f < fend) {
+            int t = 0, hi = NT;
+            while (hi - t > 1) {
+                int mid = (t + hi) >> 1;
+                if (L.off[mid] <= f) t = mid; else hi = mid;
+            }
+            int32_t seg_end = L.off[t + 1];
+            int64_t q = L.bstart[t] + (f - L.off[t]);
+            for (; f < fend; f += U) {
+                int64_t qq[U];
+                int tt[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (f + u < fend) {
+                        while (f + u >= seg_end) {
+                            ++t;
+                            seg_end = L.off[t + 1];
+                            q = L.bstart[t];
+                        }
+                        qq[u] = q++;
+                        tt[u] = t;
+                    }
+                }
+                X x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (f + u < fend) x[u] = load(qq[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (f + u < fend) apply(tt[u], x[u]);
+            }
         }
         __syncthreads();
     }

@@ -18,11 +18,16 @@ struct BinParams {
     int32_t hash_max_flops;   // symbolic hash limit
     int32_t hash_max_nnz;     // numeric hash limit
     int32_t dense_ok;         // symbolic LDS bitmap allowed (n <= 2^19)
+    int32_t rank_max_log2;    // numeric rank-space accumulator: largest capacity (log2), 0 = off
+    int32_t chunk_counts;     // the bitmap pass records per-chunk counts for the numeric chunks
     int64_t ncols;            // n
 };
 
-constexpr int NBINS = 13;
+constexpr int NBINS = 16;
 constexpr int BIN_EMPTY = 0, BIN_TINY = 1, BIN_SMALL = 2, BIN_HASH0 = 3, BIN_DENSE = 12;
+constexpr int BIN_DENSE_PAR = 11;  // numeric: column chunks of one row in parallel
+constexpr int BIN_RANK0 = 13;  // rank-space accumulator, capacity 4096 << (b - BIN_RANK0)
+constexpr int RANK_MIN_LOG2 = 12;
 constexpr int LONG_ROW = 512;
 constexpr int HASH_MIN_LOG2 = 7;  // 128 slots
 
@@ -46,17 +51,25 @@ __device__ inline int sym_bin(int64_t flops, int64_t annz, const BinParams& bp) 
     return BIN_DENSE;
 }
 
-// Numeric bin from the exact output count.
-__device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, const BinParams& bp) {
+// Numeric bin from the exact output count.  Rows whose symbolic pass kept
+// a full-width bitmap (sym_dense) reuse it: their values accumulate in LDS
+// indexed by output rank when the count fits the largest capacity.
+__device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, bool sym_dense,
+                              const BinParams& bp) {
     if (cnt == 0) return BIN_EMPTY;
     if (annz == 1) return BIN_TINY;
     if (flops <= bp.small_max_flops) return BIN_SMALL;
+    if (sym_dense && bp.rank_max_log2 && cnt <= (1ll << bp.rank_max_log2)) {
+        int lg = ceil_log2_i64(cnt);
+        if (lg < RANK_MIN_LOG2) lg = RANK_MIN_LOG2;
+        return BIN_RANK0 + (lg - RANK_MIN_LOG2);
+    }
     if (cnt <= bp.hash_max_nnz) {
         int lg = ceil_log2_i64(2 * cnt);
         if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
         return BIN_HASH0 + (lg - HASH_MIN_LOG2);
     }
-    return BIN_DENSE;
+    return (sym_dense && bp.chunk_counts) ? BIN_DENSE_PAR : BIN_DENSE;
 }
 
 struct RowInfoOut {
@@ -231,7 +244,7 @@ __global__ void __launch_bounds__(256) k_num_classify(int64_t m, const int64_t* 
         int64_t cnt = c_rp[i + 1] - c_rp[i];
         int64_t an = a_end[i] - a_beg[i];
         int64_t f = flops[i];
-        int b = num_bin(f, an, cnt, bp);
+        int b = num_bin(f, an, cnt, bin[i] == BIN_DENSE, bp);
         bin[i] = (uint8_t)b;
         atomicAdd(&s_hist[b], 1);
         atomicAdd((unsigned long long*)&s_flops[b], (unsigned long long)f);

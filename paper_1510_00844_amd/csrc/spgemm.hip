@@ -93,7 +93,7 @@ struct spg_plan_s {
 
     // per-row state of the current product
     DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
-    DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr;
+    DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save;
     int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
     LayerDesc* h_layers = nullptr; // pinned staging for merge descriptors
     int h_layers_cap = 0;
@@ -150,6 +150,9 @@ static spg_status launch(spg_plan P, const std::string& name, F&& f) {
 }
 
 static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// static LDS of k_num_rank<*, 512> (A values, product offsets, scan scratch), with margin
+static const int RANK_STATIC_LDS = (int)(8 * 512 + sizeof(ProductLds<512>) + 4 * 16 + 256);
 
 // ---------------------------------------------------------------------------
 // public helpers
@@ -208,9 +211,9 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 2048]");
     }
-    if (P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096) {
+    if (P->opts.dense_chunk_cols != 16384 && P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096) {
         delete P;
-        return fail(SPG_ERR_ARG, "dense_chunk_cols must be 4096 or 8192");
+        return fail(SPG_ERR_ARG, "dense_chunk_cols must be 4096, 8192 or 16384");
     }
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
@@ -225,9 +228,15 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         hipGetLastError();
         return fail(SPG_ERR_OOM, "pinned host allocation failed");
     }
-    // LDS beyond 64 KiB for the dynamic-bitmap kernel
+    // LDS beyond 64 KiB for the kernels sized at launch
     hipFuncSetAttribute((const void*)k_sym_bitmap<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         std::max(0, P->max_lds - (int)sizeof(ProductLds<512>) - 64));
+    hipFuncSetAttribute((const void*)k_num_rank<SR_F64, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        std::max(0, P->max_lds - RANK_STATIC_LDS));
+    hipFuncSetAttribute((const void*)k_num_rank<SR_I64, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        std::max(0, P->max_lds - RANK_STATIC_LDS));
+    hipFuncSetAttribute((const void*)k_num_rank<SR_BOOL, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        std::max(0, P->max_lds - RANK_STATIC_LDS));
     hipGetLastError();
     *out = P;
     return SPG_OK;
@@ -238,7 +247,7 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
     hipStreamSynchronize(P->stream);
     for (DevBuf* b : {&P->a_beg, &P->a_end, &P->flops, &P->maxb, &P->bin, &P->lists, &P->long_rows,
                       &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
-                      &P->mbin, &P->mlists, &P->mstats, &P->mctr})
+                      &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save})
         b->release();
     if (P->h_stats) hipHostFree(P->h_stats);
     if (P->h_layers) hipHostFree(P->h_layers);
@@ -364,6 +373,19 @@ static BinParams bin_params(spg_plan P, int64_t n) {
     const int64_t bitmap_bytes = ((n + 31) / 32) * 4;
     bp.dense_ok = (n <= (1 << 19)) && (bitmap_bytes + (int64_t)sizeof(ProductLds<512>) + 256 <= P->max_lds);
     bp.ncols = n;
+    // the bitmap pass records per-chunk counts of the numeric column chunks
+    const int64_t W = P->opts.dense_chunk_cols;
+    bp.chunk_counts = bp.dense_ok && ((n + W - 1) / W) <= MAX_CHUNKS;
+    // rank-space accumulator: (bits, prefix) words + capacity values must fit
+    bp.rank_max_log2 = 0;
+    if (bp.dense_ok) {
+        const int64_t words = 2 * bitmap_bytes;
+        for (int lg = 14; lg >= RANK_MIN_LOG2; --lg)
+            if (words + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) {
+                bp.rank_max_log2 = lg;
+                break;
+            }
+    }
     return bp;
 }
 
@@ -457,9 +479,27 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
             }));
         } else if (bb == BIN_DENSE) {
             const int32_t nwords = (int32_t)((n + 31) / 32);
+            uint32_t* save = nullptr;
+            int32_t* hidx = nullptr;
+            int32_t* csave = nullptr;
+            const int32_t W = P->opts.dense_chunk_cols;
+            const int32_t nchunks = (int32_t)((n + W - 1) / W);
+            if (bp.rank_max_log2 || bp.chunk_counts) {
+                SPG_TRY(P->heavy_idx.ensure(4 * (size_t)std::max<int64_t>(m, 1), "bitmap slots"));
+                hidx = P->heavy_idx.as<int32_t>();
+            }
+            if (bp.rank_max_log2) {
+                SPG_TRY(P->bm_save.ensure((size_t)nr * nwords * 4, "row bitmaps"));
+                save = P->bm_save.as<uint32_t>();
+            }
+            if (bp.chunk_counts) {
+                SPG_TRY(P->chunk_save.ensure((size_t)nr * nchunks * 4, "chunk counts"));
+                csave = P->chunk_save.as<int32_t>();
+            }
             SPG_TRY(launch(P, "sym_bitmap", [&] {
                 k_sym_bitmap<512><<<(unsigned)nr, 512, (size_t)nwords * 4, P->stream>>>(
-                    a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords);
+                    a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords, save, hidx, csave,
+                    W / 32, nchunks);
             }));
         } else {
             SPG_TRY(sym_hash_dispatch(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, cnt));
@@ -532,6 +572,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
     const int W = P->opts.dense_chunk_cols;
+    bool split_built = false;
     int64_t off = 0;
     for (int bb = 0; bb < NBINS; ++bb) {
         const int64_t nr = P->num_counts[bb];
@@ -546,30 +587,58 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             SPG_TRY(launch(P, "num_small", [&] {
                 k_num_small<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval);
             }));
-        } else if (bb == BIN_DENSE) {
+        } else if (bb >= BIN_RANK0) {
+            const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
+            const int64_t cap = 4096ll << (bb - BIN_RANK0);
+            const size_t lds = (size_t)nwords * 8 + (size_t)cap * sizeof(typename Sr<SR>::acc_t);
+            SPG_TRY(launch(P, "num_rank" + std::to_string(cap), [&] {
+                k_num_rank<SR, 512><<<(unsigned)nr, 512, lds, P->stream>>>(
+                    a, b, rows, ab, ae, P->bm_save.as<uint32_t>(), P->heavy_idx.as<int32_t>(), nwords, crp, ccol,
+                    cval);
+            }));
+        } else if (bb == BIN_DENSE || bb == BIN_DENSE_PAR) {
+            const bool par = bb == BIN_DENSE_PAR;
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             P->dense_chunks = chunks;
             const int32_t* split = nullptr;
             if (chunks > 1) {
-                const int64_t entries = b.nrows * (int64_t)(chunks + 1);
-                SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
-                int32_t* sp = P->split.as<int32_t>();
-                if (entries > 0) {
-                    SPG_TRY(launch(P, "split_table", [&] {
-                        k_split_table<<<grid_for(entries, 256), 256, 0, P->stream>>>(b, W, chunks, sp);
-                    }));
+                if (!split_built) {
+                    const int64_t entries = b.nrows * (int64_t)(chunks + 1);
+                    SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
+                    if (entries > 0) {
+                        int32_t* sp = P->split.as<int32_t>();
+                        SPG_TRY(launch(P, "split_table", [&] {
+                            k_split_table<<<grid_for(entries, 256), 256, 0, P->stream>>>(b, W, chunks, sp);
+                        }));
+                    }
+                    split_built = true;
                 }
-                split = sp;
+                split = P->split.as<int32_t>();
             }
-            if (W == 8192) {
-                SPG_TRY(launch(P, "num_dense", [&] {
-                    k_num_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks,
-                                                                                    crp, ccol, cval);
+            const int32_t* cc = P->chunk_save.as<int32_t>();
+            const int32_t* hi = P->heavy_idx.as<int32_t>();
+            const unsigned grid = (unsigned)(par ? nr * chunks : nr);
+            const std::string name = par ? "num_dense_par" : "num_dense";
+            if (W == 16384) {
+                SPG_TRY(launch(P, name, [&] {
+                    if (par)
+                        k_num_dense<SR, 1024, 16384, true><<<grid, 1024, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                    else
+                        k_num_dense<SR, 1024, 16384, false><<<grid, 1024, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                }));
+            } else if (W == 8192) {
+                SPG_TRY(launch(P, name, [&] {
+                    if (par)
+                        k_num_dense<SR, 512, 8192, true><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                    else
+                        k_num_dense<SR, 512, 8192, false><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
             } else {
-                SPG_TRY(launch(P, "num_dense", [&] {
-                    k_num_dense<SR, 512, 4096><<<(unsigned)nr, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks,
-                                                                                    crp, ccol, cval);
+                SPG_TRY(launch(P, name, [&] {
+                    if (par)
+                        k_num_dense<SR, 512, 4096, true><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                    else
+                        k_num_dense<SR, 512, 4096, false><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
             }
         } else {

@@ -15,6 +15,7 @@
 namespace spg {
 
 constexpr int32_t EMPTY_KEY = -1;
+constexpr int MAX_CHUNKS = 128;  // column chunks per row recorded by the bitmap pass
 
 // Locate, for each lane, the product with flat index = lane among the row's
 // products (<= 64 of them): returns the A index p and B index q.  The A row
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* ro
     for (int t = threadIdx.x; t < T; t += NT) tab[t] = EMPTY_KEY;
     __syncthreads();
     int32_t mine = 0;
-    for_each_product<NT>(
+    for_each_product_u<NT, 4>(
         a_beg[i], a_end[i], L,
         [&](int64_t p, int64_t& bs, int32_t& len) {
             int64_t k = A.col[p];
@@ -76,8 +77,8 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* ro
             len = (int32_t)(B.rp[k + 1] - bs);
         },
         [&](int, int64_t) {},
-        [&](int, int64_t, int64_t q) {
-            const int32_t j = B.col[q];
+        [&](int64_t q) { return B.col[q]; },
+        [&](int, int32_t j) {
             uint32_t h = hash_slot(j, LOG2T);
             while (true) {
                 int32_t cur = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -97,19 +98,26 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* ro
     if (threadIdx.x == 0) cnt[i] = total;
 }
 
-// Dynamic LDS: `nwords` 32-bit bitmap words covering columns [0, n).
+// Dynamic LDS: `nwords` 32-bit bitmap words covering columns [0, n).  Bits
+// are set without reading them back; the count is the popcount at the end.
+// The finished bitmap is the row's stored set; it is written to bm_save
+// (slot = position in the bin list, recorded in heavy_idx) so the numeric
+// pass can place values by rank without gathering the columns again.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* rows,
                                                    const int64_t* a_beg, const int64_t* a_end,
-                                                   int64_t* cnt, int32_t nwords) {
+                                                   int64_t* cnt, int32_t nwords, uint32_t* bm_save,
+                                                   int32_t* heavy_idx, int32_t* chunk_save,
+                                                   int32_t chunk_words, int32_t nchunks) {
     extern __shared__ uint32_t bm[];
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
+    __shared__ int32_t s_chunk[MAX_CHUNKS];
     const int64_t i = rows[blockIdx.x];
     for (int t = threadIdx.x; t < nwords; t += NT) bm[t] = 0u;
+    for (int t = threadIdx.x; t < MAX_CHUNKS; t += NT) s_chunk[t] = 0;
     __syncthreads();
-    int32_t mine = 0;
-    for_each_product<NT>(
+    for_each_product_u<NT, 8>(
         a_beg[i], a_end[i], L,
         [&](int64_t p, int64_t& bs, int32_t& len) {
             int64_t k = A.col[p];
@@ -117,14 +125,24 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
             len = (int32_t)(B.rp[k + 1] - bs);
         },
         [&](int, int64_t) {},
-        [&](int, int64_t, int64_t q) {
-            const uint32_t j = (uint32_t)B.col[q];
-            const uint32_t bit = 1u << (j & 31);
-            uint32_t old = atomicOr(&bm[j >> 5], bit);
-            mine += (old & bit) ? 0 : 1;
-        });
-    int32_t total = block_reduce_add<NT, int32_t>(mine, red);
-    if (threadIdx.x == 0) cnt[i] = total;
+        [&](int64_t q) { return (uint32_t)B.col[q]; },
+        [&](int, uint32_t j) { atomicOr(&bm[j >> 5], 1u << (j & 31)); });
+    int32_t mine = 0;
+    uint32_t* dst = bm_save ? bm_save + (int64_t)blockIdx.x * nwords : nullptr;
+    for (int t = threadIdx.x; t < nwords; t += NT) {
+        const uint32_t w = bm[t];
+        const int pc = __popc(w);
+        mine += pc;
+        if (dst) dst[t] = w;
+        if (chunk_save && pc) atomicAdd(&s_chunk[t / chunk_words], pc);
+    }
+    int32_t total = block_reduce_add<NT, int32_t>(mine, red);  // barriers: s_chunk complete
+    if (threadIdx.x == 0) {
+        cnt[i] = total;
+        if (heavy_idx) heavy_idx[i] = (int32_t)blockIdx.x;
+    }
+    if (chunk_save)
+        for (int c = threadIdx.x; c < nchunks; c += NT) chunk_save[(int64_t)blockIdx.x * nchunks + c] = s_chunk[c];
 }
 
 }  // namespace spg

@@ -54,8 +54,12 @@ def _binned_matrices(seed=7):
     """A (m x K) whose rows cover every accumulator bin against an R-MAT B
     with hub rows: empty rows, one-entry rows, a few products, each hash
     size, and rows whose products exceed the hash limit."""
-    B = synth.rmat(13, 16, synth.G500, seed=seed)
-    K = B.nrows
+    # B: the first 8192 rows of an R-MAT scale-16 matrix (65536 columns, so
+    # rows up to 2048 products stay in the hash bins and hub rows appear)
+    R = synth.rmat(16, 16, synth.G500, seed=seed)
+    K = 8192
+    B = synth.CSR(K, R.ncols, R.row_ptr[:K + 1].copy(), R.col[:R.row_ptr[K]].copy(),
+                  R.val[:R.row_ptr[K]].copy())
     rng = np.random.default_rng(seed)
     blen = np.diff(B.row_ptr)
     order = np.argsort(-blen)
@@ -117,7 +121,10 @@ def test_every_bin_full(plan, sr):
     used_num = [b for b in range(spg.NBINS) if st["num_rows"][b]]
     for b in (0, 1, 2, 3, 4, 5, 6, 7, 8, 12):
         assert b in used_sym or b in used_num, "bin %s not exercised" % spg.BIN_NAMES[b]
-    assert 12 in used_num and 12 in used_sym
+    assert 12 in used_sym
+    assert any(b in used_num for b in (13, 14, 15)), "no rank-space rows"
+    for b in (6, 7, 8):
+        assert b in used_num, "numeric bin %s not exercised" % spg.BIN_NAMES[b]
     check_full_vs_oracle(C, A, B, sr)
 
 
@@ -180,11 +187,25 @@ def test_all_products_in_one_column(plan):
         check_full_vs_oracle(run(plan, sr, AA, BB), AA, BB, sr)
 
 
-def test_dense_operands(plan):
-    """Fully dense small operands: every row is heavy; output rows are dense."""
+@pytest.mark.parametrize("ncols,want", [(9000, 15), (20000, 11), (262144, 12)])
+def test_dense_operands(plan, ncols, want):
+    """Large output rows.  Dense operands with 9000 columns fit the
+    rank-space accumulator (bin rank16384); with 20000 outputs per row they
+    take parallel column chunks (dense_par); with 262144 columns and 20
+    entries per B row the symbolic pass uses a hash table, so the numeric
+    pass sweeps the column chunks of a row in one workgroup (dense)."""
     A = synth.random_csr(40, 300, 1.0, 5, "f64")
-    B = synth.random_csr(300, 9000, 1.0, 6, "f64")
-    check_full_vs_oracle(run(plan, "f64", A, B), A, B, "f64")
+    if ncols < 100000:
+        B = synth.random_csr(300, ncols, 1.0, 6, "f64")
+    else:
+        rng = np.random.default_rng(6)
+        rr = np.repeat(np.arange(300), 20)
+        cc = np.concatenate([rng.choice(ncols, 20, replace=False) for _ in range(300)])
+        B = synth.canonical_from_coo(300, ncols, rr, cc, rng.random(rr.size), dup="first")
+    C = run(plan, "f64", A, B)
+    st = plan.stats()
+    assert st["num_rows"][want] == 40, st["num_rows"]
+    check_full_vs_oracle(C, A, B, "f64")
 
 
 def test_rmat_s16_c2(plan):
