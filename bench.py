@@ -35,7 +35,26 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
     ap.add_argument("--dense-cols", type=int, default=0, help="columns per dense accumulator chunk")
+    ap.add_argument("--streams", type=int, default=0, help="streams for independent bins (1..4)")
+    ap.add_argument("--gather-map", type=int, default=0, help="1 coalesced, 2 per-lane ranges")
+    ap.add_argument("--unroll", type=int, default=0, help="gathers in flight per lane (4 or 8)")
+    ap.add_argument("--sym-gather-map", type=int, default=0)
+    ap.add_argument("--sym-unroll", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB (3 times), the reference for "
+                         "scaling the HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
 def value_width(sr):
@@ -88,6 +107,9 @@ def model_bytes(m, annz, flops, cnnz, sr):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
               "(run with --gpus 1)" % args.gpus, file=sys.stderr)
@@ -104,7 +126,9 @@ def main():
     A = synth.rmat(args.scale, 16, synth.G500, seed=2)
     sr = "f64"
     dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
-    plan = spg.Plan(profile=not args.no_profile, dense_chunk_cols=args.dense_cols)
+    plan = spg.Plan(profile=not args.no_profile, dense_chunk_cols=args.dense_cols, streams=args.streams,
+                    gather_map=args.gather_map, unroll=args.unroll, sym_gather_map=args.sym_gather_map,
+                    sym_unroll=args.sym_unroll)
 
     def step():
         rp, nnz = spg.spgemm_symbolic(plan, sr, dA, dA)

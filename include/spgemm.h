@@ -79,7 +79,13 @@ typedef struct {
     int32_t hash_max_nnz;      /* numeric: LDS hash table up to this many outputs per row */
     int32_t dense_chunk_cols;  /* numeric dense rows: columns per LDS chunk (power of two) */
     int32_t profile;           /* 1: time every kernel launch with HIP events */
-    int32_t reserved[10];
+    int32_t streams;           /* streams independent bins are spread over (1..4) */
+    int32_t gather_map;        /* numeric heavy rows, products per lane: 1 = neighbouring lanes take
+                                  neighbouring products (coalesced), 2 = each lane a contiguous range */
+    int32_t unroll;            /* numeric heavy rows: gathers in flight per lane (4 or 8) */
+    int32_t sym_gather_map;    /* the same two choices for the symbolic bitmap rows */
+    int32_t sym_unroll;
+    int32_t reserved[5];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;

@@ -43,7 +43,9 @@ class Opts(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("small_max_flops", ctypes.c_int32),
                 ("hash_max_flops", ctypes.c_int32), ("hash_max_nnz", ctypes.c_int32),
                 ("dense_chunk_cols", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 10)]
+                ("streams", ctypes.c_int32), ("gather_map", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("sym_gather_map", ctypes.c_int32), ("sym_unroll", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -142,7 +144,7 @@ class Plan:
 
     def __init__(self, device=None, stream: Optional[torch.cuda.Stream] = None, validate=False,
                  profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
-                 dense_chunk_cols=0):
+                 dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0):
         L = lib()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
@@ -152,7 +154,9 @@ class Plan:
             o.validate = int(validate)
             o.profile = int(profile)
             for name, v in (("small_max_flops", small_max_flops), ("hash_max_flops", hash_max_flops),
-                            ("hash_max_nnz", hash_max_nnz), ("dense_chunk_cols", dense_chunk_cols)):
+                            ("hash_max_nnz", hash_max_nnz), ("dense_chunk_cols", dense_chunk_cols),
+                            ("streams", streams), ("gather_map", gather_map), ("unroll", unroll),
+                            ("sym_gather_map", sym_gather_map), ("sym_unroll", sym_unroll)):
                 if v:
                     setattr(o, name, int(v))
             h = ctypes.c_void_p()

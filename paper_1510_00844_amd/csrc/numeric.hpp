@@ -254,8 +254,8 @@ __global__ void __launch_bounds__(256) k_split_table(Csr B, int32_t W, int32_t P
 // the row offset plus the counts of the earlier chunks recorded by the
 // symbolic bitmap pass (chunk_cnt, slot heavy_idx[i]), so chunks of one
 // row run side by side and the largest rows do not serialize the kernel.
-template <int SR, int NT, int W, bool PAR>
-__global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* rows,
+template <int SR, int NT, int W, bool PAR, int GM>
+__global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* rows, int64_t nrows,
                                                   const int64_t* a_beg, const int64_t* a_end,
                                                   const int32_t* split, int32_t P,
                                                   const int32_t* chunk_cnt, const int32_t* heavy_idx,
@@ -269,21 +269,25 @@ __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* r
     __shared__ V s_av[NT];
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
-    const int64_t i = rows[PAR ? blockIdx.x / P : blockIdx.x];
+    // the accumulator is cleared once; emission resets exactly the slots it
+    // reads, so later chunks (and later work items) start from zero again
+    for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
+    for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
+    // work items: rows (PAR = false) or (row, chunk) pairs, grid-stride so
+    // the grid stays small however many chunks there are
+    const int64_t items = PAR ? (int64_t)nrows * P : (int64_t)nrows;
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t i = rows[PAR ? item / P : item];
     const int64_t beg = a_beg[i], end = a_end[i];
     int64_t off = c_rp[i];
     const int64_t row_end = c_rp[i + 1];
     int c_first = 0, c_last = P;
     if (PAR) {
-        c_first = blockIdx.x % P;
+        c_first = (int)(item % P);
         c_last = c_first + 1;
         const int32_t* cc = chunk_cnt + (int64_t)heavy_idx[i] * P;
         for (int c = 0; c < c_first; ++c) off += cc[c];
     }
-    // the accumulator is cleared once; emission resets exactly the slots it
-    // reads, so later chunks start from zero again
-    for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
-    for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
     // Rows with at most NT entries in the window keep their A entry (column
     // k, start of B(k,:), position reached in B(k,:)) in registers across
     // the chunks, so each chunk costs one split-table load per entry.
@@ -299,7 +303,7 @@ __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* r
     __syncthreads();
     for (int c = c_first; c < c_last; ++c) {
         const int32_t cbase = c * W;
-        for_each_product_u<NT, 4>(
+        for_each_product_gm<NT, GM>(
             beg, end, L,
             [&](int64_t p, int64_t& bs, int32_t& len) {
                 if (single) {
@@ -352,11 +356,12 @@ __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* r
         off += chunk_total;
         __syncthreads();
     }
+    }
 }
 
 // Dynamic LDS: nwords 64-bit words (bits in the low half, count of set bits
 // in all earlier words in the high half), then `cap` accumulators.
-template <int SR, int NT>
+template <int SR, int NT, int GM>
 __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* rows,
                                                  const int64_t* a_beg, const int64_t* a_end,
                                                  const uint32_t* bm_save, const int32_t* heavy_idx,
@@ -394,7 +399,7 @@ __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* ro
     }
     for (int r = threadIdx.x; r < cnt; r += NT) acc[r] = S::zero();
     __syncthreads();
-    for_each_product_u<NT, 4>(
+    for_each_product_gm<NT, GM>(
         a_beg[i], a_end[i], L,
         [&](int64_t p, int64_t& bs, int32_t& len) {
             int64_t k = A.col[p];

@@ -66,12 +66,9 @@ __device__ inline void for_each_product(int64_t a_beg, int64_t a_end, ProductLds
     }
 }
 
-// Same enumeration, with the gathers of U consecutive products of a thread
-// issued back to back before any of them is applied: `load(q)` reads what
-// the product needs from B, `apply(t, x)` consumes it.  Keeping U loads in
-// flight per thread is what hides the gather latency.
+// Thread-contiguous variant: thread t walks products [t*per, (t+1)*per).
 template <int NT, int U, class Seg, class Pre, class Load, class Apply>
-__device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
+__device__ inline void for_each_product_t(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
                                           Pre pre, Load load, Apply apply) {
     typedef decltype(load((int64_t)0)) X;
     for (int64_t base = a_beg; base < a_end; base += NT) {
@@ -125,6 +122,110 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
         }
         __syncthreads();
     }
+}
+
+// Same enumeration, mapped for coalesced gathers: each wave takes an equal
+// contiguous range of the batch's products and its lanes take consecutive
+// products, 64 at a time, so one load instruction reads 64 neighbouring B
+// entries.  A step of 64 products that lies inside one segment (the common
+// case for long B rows) needs a single comparison to locate; otherwise each
+// lane binary-searches the segment offsets from the current segment on.
+// U steps are gathered (`load(q)`) before any is applied (`apply(t, x)`), so
+// each lane keeps U loads in flight.
+// With COAL = false each thread instead takes its own contiguous range of
+// products (one search per thread, U consecutive products per step): lanes
+// then touch different segments, which spreads LDS atomics over more
+// addresses at the price of uncoalesced gathers.
+template <int NT, int U, bool COAL = true, class Seg, class Pre, class Load, class Apply>
+__device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
+                                          Pre pre, Load load, Apply apply) {
+    typedef decltype(load((int64_t)0)) X;
+    if (!COAL) {
+        for_each_product_t<NT, U>(a_beg, a_end, L, seg, pre, load, apply);
+        return;
+    }
+    constexpr int NW = NT / SPG_WAVE;
+    const int lane = lane_id();
+    const int wid = threadIdx.x / SPG_WAVE;
+    for (int64_t base = a_beg; base < a_end; base += NT) {
+        const int64_t p = base + threadIdx.x;
+        int64_t bs = 0;
+        int32_t len = 0;
+        if (p < a_end) {
+            seg(p, bs, len);
+            pre((int)threadIdx.x, p);
+        }
+        int32_t total;
+        int32_t off = block_exclusive_scan<NT, int32_t>(len, &total, L.tmp);
+        L.off[threadIdx.x] = off;
+        L.bstart[threadIdx.x] = bs;
+        if (threadIdx.x == 0) L.off[NT] = total;
+        __syncthreads();
+        const int32_t span = (total + NW - 1) / NW;
+        const int32_t f0 = wid * span;
+        const int32_t f1 = f0 + span < total ? f0 + span : total;
+        if (f0 < f1) {
+            // segment of the range start (same for every lane: broadcast reads)
+            int ta = 0;
+            {
+                int hi = NT;
+                while (hi - ta > 1) {
+                    int mid = (ta + hi) >> 1;
+                    if (L.off[mid] <= f0) ta = mid; else hi = mid;
+                }
+            }
+            for (int32_t fb = f0; fb < f1; fb += SPG_WAVE * U) {
+                int64_t qq[U];
+                int tt[U];
+                bool ok[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t fs = fb + u * SPG_WAVE;  // first product of this step
+                    const int32_t f = fs + lane;
+                    ok[u] = f < f1;
+                    const int32_t flast = (fs + SPG_WAVE - 1 < f1 ? fs + SPG_WAVE - 1 : f1 - 1);
+                    int t = ta;
+                    if (fs < f1 && flast >= L.off[ta + 1]) {
+                        // a segment boundary falls inside the step
+                        int hi = NT;
+                        while (hi - t > 1) {
+                            int mid = (t + hi) >> 1;
+                            if (L.off[mid] <= f) t = mid; else hi = mid;
+                        }
+                        // next step starts in the segment of this step's last product
+                        int tl = ta, h2 = NT;
+                        while (h2 - tl > 1) {
+                            int mid = (tl + h2) >> 1;
+                            if (L.off[mid] <= flast) tl = mid; else h2 = mid;
+                        }
+                        ta = tl;
+                    }
+                    tt[u] = t;
+                    qq[u] = L.bstart[t] + (f - L.off[t]);
+                }
+                X x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) x[u] = load(qq[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) apply(tt[u], x[u]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Gather mode of the heavy-row kernels (a tuning choice):
+//   0: coalesced, 4 steps in flight   1: coalesced, 8 steps in flight
+//   2: per-thread ranges, 4 in flight 3: per-thread ranges, 8 in flight
+template <int NT, int GM, class Seg, class Pre, class Load, class Apply>
+__device__ inline void for_each_product_gm(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
+                                           Pre pre, Load load, Apply apply) {
+    if constexpr (GM == 0) for_each_product_u<NT, 4, true>(a_beg, a_end, L, seg, pre, load, apply);
+    else if constexpr (GM == 1) for_each_product_u<NT, 8, true>(a_beg, a_end, L, seg, pre, load, apply);
+    else if constexpr (GM == 2) for_each_product_u<NT, 4, false>(a_beg, a_end, L, seg, pre, load, apply);
+    else for_each_product_u<NT, 8, false>(a_beg, a_end, L, seg, pre, load, apply);
 }
 
 }  // namespace spg

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -85,9 +86,14 @@ struct Signature {
     }
 };
 
+constexpr int NAUX = 3;  // helper streams for independent bins
+
 struct spg_plan_s {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the caller's stream: every call is ordered on it
+    hipStream_t cur = nullptr;     // stream the next launch goes to
+    hipStream_t aux[NAUX] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[NAUX] = {};
     spg_opts opts;
     int max_lds = 65536;
 
@@ -131,22 +137,56 @@ static hipEvent_t take_event(spg_plan P) {
     return e;
 }
 
+static inline hipStream_t cs(spg_plan P) { return P->cur ? P->cur : P->stream; }
+
 template <class F>
 static spg_status launch(spg_plan P, const std::string& name, F&& f) {
     hipEvent_t b = nullptr, e = nullptr;
+    hipStream_t st = P->cur ? P->cur : P->stream;
     if (P->opts.profile) {
         b = take_event(P);
         e = take_event(P);
-        hipEventRecord(b, P->stream);
+        hipEventRecord(b, st);
     }
     f();
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(SPG_ERR_HIP, std::string("launch ") + name + ": " + hipGetErrorString(err));
     if (P->opts.profile) {
-        hipEventRecord(e, P->stream);
+        hipEventRecord(e, st);
         P->prof_pending.push_back({name, b, e});
     }
     return SPG_OK;
+}
+
+// Fork: helper streams wait for everything queued so far on the caller's
+// stream.  Join: the caller's stream waits for the helpers.  Between the two,
+// independent bins are spread over the streams so their kernels overlap.
+static spg_status fork_streams(spg_plan P) {
+    HIP_TRY(hipEventRecord(P->ev_fork, P->stream));
+    for (int k = 0; k < NAUX; ++k) HIP_TRY(hipStreamWaitEvent(P->aux[k], P->ev_fork, 0));
+    return SPG_OK;
+}
+static spg_status join_streams(spg_plan P) {
+    for (int k = 0; k < NAUX; ++k) {
+        HIP_TRY(hipEventRecord(P->ev_join[k], P->aux[k]));
+        HIP_TRY(hipStreamWaitEvent(P->stream, P->ev_join[k], 0));
+    }
+    P->cur = nullptr;
+    return SPG_OK;
+}
+static void use_stream(spg_plan P, int slot) {
+    slot %= P->opts.streams;
+    P->cur = slot == 0 ? P->stream : P->aux[slot - 1];
+}
+
+// Order of the non-empty bins by work, largest first, so the heaviest
+// kernels start on different streams.
+static std::vector<int> bins_by_work(const int64_t* rows, const int64_t* work) {
+    std::vector<int> order;
+    for (int b = 0; b < NBINS; ++b)
+        if (rows[b] > 0) order.push_back(b);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    return order;
 }
 
 static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -166,6 +206,12 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->hash_max_nnz = 2048;
     o->dense_chunk_cols = 8192;
     o->profile = 0;
+    o->streams = 4;
+    o->gather_map = 1;
+    o->unroll = 4;
+    o->sym_gather_map = 2;
+    o->sym_unroll = 8;
+    o->dense_chunk_cols = 4096;
 }
 
 extern "C" const char* spg_status_string(spg_status s) {
@@ -185,6 +231,32 @@ extern "C" const char* spg_status_string(spg_status s) {
 
 extern "C" const char* spg_last_error(void) { return g_last_error.c_str(); }
 
+template <int GM>
+static void set_lds_attributes(spg_plan P) {
+    const int dyn_bitmap = std::max(0, P->max_lds - (int)sizeof(ProductLds<512>) - 64 - 4 * MAX_CHUNKS);
+    const int dyn_rank = std::max(0, P->max_lds - RANK_STATIC_LDS);
+    hipFuncSetAttribute((const void*)k_sym_bitmap<512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_bitmap);
+    hipFuncSetAttribute((const void*)k_num_rank<SR_F64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rank<SR_I64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rank<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+}
+
+static int gather_mode(int map, int unroll) { return (map == 2 ? 2 : 0) + (unroll == 8 ? 1 : 0); }
+
+// Call f(std::integral_constant<int, GM>) for the plan's gather mode of the
+// numeric (sym = false) or symbolic heavy-row kernels.
+template <class F>
+static spg_status with_gm(spg_plan P, F&& f, bool sym = false) {
+    const int gm = sym ? gather_mode(P->opts.sym_gather_map, P->opts.sym_unroll)
+                       : gather_mode(P->opts.gather_map, P->opts.unroll);
+    switch (gm) {
+        case 0: return f(std::integral_constant<int, 0>());
+        case 1: return f(std::integral_constant<int, 1>());
+        case 2: return f(std::integral_constant<int, 2>());
+        default: return f(std::integral_constant<int, 3>());
+    }
+}
+
 extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opts* opts) {
     if (!out) return fail(SPG_ERR_ARG, "plan pointer is NULL");
     *out = nullptr;
@@ -198,6 +270,18 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         if (!P->opts.hash_max_flops) P->opts.hash_max_flops = d.hash_max_flops;
         if (!P->opts.hash_max_nnz) P->opts.hash_max_nnz = d.hash_max_nnz;
         if (!P->opts.dense_chunk_cols) P->opts.dense_chunk_cols = d.dense_chunk_cols;
+        if (!P->opts.streams) P->opts.streams = d.streams;
+        if (!P->opts.gather_map) P->opts.gather_map = d.gather_map;
+        if (!P->opts.unroll) P->opts.unroll = d.unroll;
+        if (!P->opts.sym_gather_map) P->opts.sym_gather_map = d.sym_gather_map;
+        if (!P->opts.sym_unroll) P->opts.sym_unroll = d.sym_unroll;
+    }
+    auto map_ok = [](int m) { return m == 1 || m == 2; };
+    auto unroll_ok = [](int u) { return u == 4 || u == 8; };
+    if (P->opts.streams < 1 || P->opts.streams > NAUX + 1 || !map_ok(P->opts.gather_map) ||
+        !map_ok(P->opts.sym_gather_map) || !unroll_ok(P->opts.unroll) || !unroll_ok(P->opts.sym_unroll)) {
+        delete P;
+        return fail(SPG_ERR_ARG, "streams must be 1..4, gather maps 1 or 2, unroll 4 or 8");
     }
     if (P->opts.small_max_flops < 0 || P->opts.small_max_flops > 64) {
         delete P;
@@ -223,20 +307,29 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
         P->max_lds = lds;
+    for (int k = 0; k < NAUX; ++k) {
+        if (hipStreamCreateWithFlags(&P->aux[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&P->ev_join[k], hipEventDisableTiming) != hipSuccess) {
+            hipGetLastError();
+            delete P;
+            return fail(SPG_ERR_HIP, "helper stream creation failed");
+        }
+    }
+    if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        hipGetLastError();
+        delete P;
+        return fail(SPG_ERR_HIP, "event creation failed");
+    }
     if (hipHostMalloc((void**)&P->h_stats, sizeof(int64_t) * (4 * NBINS + 8), hipHostMallocDefault) != hipSuccess) {
         delete P;
         hipGetLastError();
         return fail(SPG_ERR_OOM, "pinned host allocation failed");
     }
     // LDS beyond 64 KiB for the kernels sized at launch
-    hipFuncSetAttribute((const void*)k_sym_bitmap<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        std::max(0, P->max_lds - (int)sizeof(ProductLds<512>) - 64));
-    hipFuncSetAttribute((const void*)k_num_rank<SR_F64, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        std::max(0, P->max_lds - RANK_STATIC_LDS));
-    hipFuncSetAttribute((const void*)k_num_rank<SR_I64, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        std::max(0, P->max_lds - RANK_STATIC_LDS));
-    hipFuncSetAttribute((const void*)k_num_rank<SR_BOOL, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        std::max(0, P->max_lds - RANK_STATIC_LDS));
+    set_lds_attributes<0>(P);
+    set_lds_attributes<1>(P);
+    set_lds_attributes<2>(P);
+    set_lds_attributes<3>(P);
     hipGetLastError();
     *out = P;
     return SPG_OK;
@@ -256,6 +349,11 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
         hipEventDestroy(r.end);
     }
     for (auto e : P->event_pool) hipEventDestroy(e);
+    for (int k = 0; k < NAUX; ++k) {
+        if (P->aux[k]) hipStreamDestroy(P->aux[k]);
+        if (P->ev_join[k]) hipEventDestroy(P->ev_join[k]);
+    }
+    if (P->ev_fork) hipEventDestroy(P->ev_fork);
     delete P;
     return SPG_OK;
 }
@@ -281,6 +379,10 @@ static spg_status check_csr(const spg_csr* M, const char* name, spg_semiring sr,
         return fail(SPG_ERR_ARG, std::string(name) + ".val is NULL");
     return SPG_OK;
 }
+
+// Row-per-workgroup launches use up to 1024 threads per row; HIP limits a
+// grid to 2^32 threads in x, so one call takes at most 2^22 rows.
+static const int64_t MAX_ROWS_PER_CALL = 1ll << 22;
 
 static Csr view(const spg_csr* M) { return Csr{M->nrows, M->ncols, M->nnz, M->row_ptr, M->col, M->val}; }
 
@@ -314,11 +416,11 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 
 static spg_status fill_i32(spg_plan P, int32_t* p, int64_t n, int32_t v) {
     if (n <= 0) return SPG_OK;
-    return launch(P, "fill", [&] { k_fill_i32<<<grid_for(n, 256), 256, 0, P->stream>>>(p, n, v); });
+    return launch(P, "fill", [&] { k_fill_i32<<<grid_for(n, 256), 256, 0, cs(P)>>>(p, n, v); });
 }
 static spg_status fill_i64(spg_plan P, int64_t* p, int64_t n, int64_t v) {
     if (n <= 0) return SPG_OK;
-    return launch(P, "fill", [&] { k_fill_i64<<<grid_for(n, 256), 256, 0, P->stream>>>(p, n, v); });
+    return launch(P, "fill", [&] { k_fill_i64<<<grid_for(n, 256), 256, 0, cs(P)>>>(p, n, v); });
 }
 
 static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
@@ -327,7 +429,7 @@ static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
     int32_t* bad = P->small_i32.as<int32_t>() + 32;
     SPG_TRY(fill_i32(P, bad, 1, 0));
     Csr v = view(M);
-    SPG_TRY(launch(P, "validate", [&] { k_validate<<<grid_for(M->nrows, 256), 256, 0, P->stream>>>(v, bad); }));
+    SPG_TRY(launch(P, "validate", [&] { k_validate<<<grid_for(M->nrows, 256), 256, 0, cs(P)>>>(v, bad); }));
     int32_t h = 0;
     HIP_TRY(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
@@ -345,9 +447,9 @@ static spg_status scan_counts(spg_plan P, int64_t* rp, int64_t m) {
     SPG_TRY(P->tiles.ensure(sizeof(int64_t) * (ntiles + 1), "scan tiles"));
     int64_t* tiles = P->tiles.as<int64_t>();
     int64_t* cnt = rp + 1;
-    SPG_TRY(launch(P, "scan", [&] { k_scan_tiles<<<(unsigned)ntiles, SCAN_NT, 0, P->stream>>>(cnt, m, tiles); }));
-    SPG_TRY(launch(P, "scan", [&] { k_scan_top<<<1, SCAN_NT, 0, P->stream>>>(tiles, ntiles); }));
-    SPG_TRY(launch(P, "scan", [&] { k_scan_apply<<<(unsigned)ntiles, SCAN_NT, 0, P->stream>>>(cnt, m, tiles, cnt); }));
+    SPG_TRY(launch(P, "scan", [&] { k_scan_tiles<<<(unsigned)ntiles, SCAN_NT, 0, cs(P)>>>(cnt, m, tiles); }));
+    SPG_TRY(launch(P, "scan", [&] { k_scan_top<<<1, SCAN_NT, 0, cs(P)>>>(tiles, ntiles); }));
+    SPG_TRY(launch(P, "scan", [&] { k_scan_apply<<<(unsigned)ntiles, SCAN_NT, 0, cs(P)>>>(cnt, m, tiles, cnt); }));
     return SPG_OK;
 }
 
@@ -397,7 +499,7 @@ static spg_status launch_sym_hash(spg_plan P, Csr A, Csr B, const int32_t* rows,
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
     return launch(P, "sym_hash" + std::to_string(1 << LOG2T), [&] {
-        k_sym_hash<NT, LOG2T><<<(unsigned)nr, NT, 0, P->stream>>>(A, B, rows, ab, ae, cnt);
+        k_sym_hash<NT, LOG2T><<<(unsigned)nr, NT, 0, cs(P)>>>(A, B, rows, ab, ae, cnt);
     });
 }
 
@@ -417,11 +519,13 @@ static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int3
 
 extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B,
                                       int64_t k_lo, int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz) {
+    if (P) P->cur = nullptr;
     if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
     if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
     SPG_TRY(check_csr(A, "A", sr, false));
     SPG_TRY(check_csr(B, "B", sr, false));
     if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
+    if (A->nrows > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split A by rows");
     if (k_lo < 0 || k_hi < k_lo || k_hi > A->ncols) return fail(SPG_ERR_ARG, "window must satisfy 0 <= k_lo <= k_hi <= A.ncols");
     if (!c_row_ptr) return fail(SPG_ERR_ARG, "c_row_ptr is NULL");
     P->have_symbolic = false;
@@ -445,13 +549,13 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                  P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr};
     if (m > 0) {
         SPG_TRY(launch(P, "rowinfo", [&] {
-            k_rowinfo<<<grid_for(m, 16), 256, 0, P->stream>>>(a, b, k_lo, k_hi, full, bp, o);
+            k_rowinfo<<<grid_for(m, 16), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "rowinfo_long", [&] {
-            k_rowinfo_long<<<256, 256, 0, P->stream>>>(a, b, k_lo, k_hi, full, bp, o);
+            k_rowinfo_long<<<256, 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "bin_scatter", [&] {
-            k_bin_scatter<<<grid_for(m, 256), 256, 0, P->stream>>>(m, P->bin.as<uint8_t>(), stats, ctr + 1,
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), stats, ctr + 1,
                                                                    P->lists.as<int32_t>());
         }));
     }
@@ -464,17 +568,22 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     if (P->sym_counts[BIN_DENSE] > 0 && !bp.dense_ok)
         return fail(SPG_ERR_INDEX_RANGE, "rows with more products than the hash limit need n <= 2^19 columns");
 
-    // per-bin accumulators
+    // per-bin accumulators, independent bins on separate streams
     const int32_t* lists = P->lists.as<int32_t>();
-    int64_t off = 0;
-    for (int bb = 0; bb < NBINS; ++bb) {
+    int64_t bin_off[NBINS + 1];
+    bin_off[0] = 0;
+    for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->sym_counts[x];
+    SPG_TRY(fork_streams(P));
+    const std::vector<int> sym_order = bins_by_work(P->sym_counts, P->sym_counts + NBINS);
+    for (size_t oi = 0; oi < sym_order.size(); ++oi) {
+        const int bb = sym_order[oi];
         const int64_t nr = P->sym_counts[bb];
-        const int32_t* rows = lists + off;
-        off += nr;
+        const int32_t* rows = lists + bin_off[bb];
         if (nr == 0 || bb == BIN_EMPTY || bb == BIN_TINY) continue;
+        use_stream(P, (int)oi);
         if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "sym_small", [&] {
-                k_sym_small<<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
+                k_sym_small<<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
                                                                      P->a_end.as<int64_t>(), cnt);
             }));
         } else if (bb == BIN_DENSE) {
@@ -496,15 +605,18 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                 SPG_TRY(P->chunk_save.ensure((size_t)nr * nchunks * 4, "chunk counts"));
                 csave = P->chunk_save.as<int32_t>();
             }
-            SPG_TRY(launch(P, "sym_bitmap", [&] {
-                k_sym_bitmap<512><<<(unsigned)nr, 512, (size_t)nwords * 4, P->stream>>>(
-                    a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords, save, hidx, csave,
-                    W / 32, nchunks);
-            }));
+            SPG_TRY(with_gm(P, [&](auto gm) {
+                return launch(P, "sym_bitmap", [&] {
+                    k_sym_bitmap<512, decltype(gm)::value><<<(unsigned)nr, 512, (size_t)nwords * 4, cs(P)>>>(
+                        a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords, save, hidx, csave,
+                        W / 32, nchunks);
+                });
+            }, true));
         } else {
             SPG_TRY(sym_hash_dispatch(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, cnt));
         }
     }
+    SPG_TRY(join_streams(P));
     SPG_TRY(scan_counts(P, c_row_ptr, m));
 
     // numeric classification from the exact counts
@@ -513,12 +625,12 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     SPG_TRY(fill_i32(P, ctr + 1, NBINS, 0));
     if (m > 0) {
         SPG_TRY(launch(P, "num_classify", [&] {
-            k_num_classify<<<grid_for(m, 256), 256, 0, P->stream>>>(m, c_row_ptr, P->a_beg.as<int64_t>(),
+            k_num_classify<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, c_row_ptr, P->a_beg.as<int64_t>(),
                                                                     P->a_end.as<int64_t>(), P->flops.as<int64_t>(),
                                                                     bp, P->bin.as<uint8_t>(), nstats);
         }));
         SPG_TRY(launch(P, "bin_scatter", [&] {
-            k_bin_scatter<<<grid_for(m, 256), 256, 0, P->stream>>>(m, P->bin.as<uint8_t>(), nstats, ctr + 1,
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), nstats, ctr + 1,
                                                                    P->lists.as<int32_t>());
         }));
     }
@@ -548,7 +660,7 @@ static spg_status launch_num_hash(spg_plan P, Csr A, Csr B, const int32_t* rows,
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
     return launch(P, "num_hash" + std::to_string(1 << LOG2T), [&] {
-        k_num_hash<SR, NT, LOG2T><<<(unsigned)nr, NT, 0, P->stream>>>(A, B, rows, ab, ae, crp, ccol, cval);
+        k_num_hash<SR, NT, LOG2T><<<(unsigned)nr, NT, 0, cs(P)>>>(A, B, rows, ab, ae, crp, ccol, cval);
     });
 }
 
@@ -572,29 +684,49 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
     const int W = P->opts.dense_chunk_cols;
+    int64_t bin_off[NBINS + 1];
+    bin_off[0] = 0;
+    for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->num_counts[x];
+    // the split table is built on the caller's stream before the fork
     bool split_built = false;
-    int64_t off = 0;
-    for (int bb = 0; bb < NBINS; ++bb) {
+    if ((P->num_counts[BIN_DENSE] || P->num_counts[BIN_DENSE_PAR]) && b.ncols > W) {
+        const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
+        const int64_t entries = b.nrows * (int64_t)(chunks + 1);
+        SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
+        if (entries > 0) {
+            int32_t* sp = P->split.as<int32_t>();
+            SPG_TRY(launch(P, "split_table", [&] {
+                k_split_table<<<grid_for(entries, 256), 256, 0, cs(P)>>>(b, W, chunks, sp);
+            }));
+        }
+        split_built = true;
+    }
+    SPG_TRY(fork_streams(P));
+    const std::vector<int> num_order = bins_by_work(P->num_counts, P->num_counts + NBINS);
+    for (size_t oi = 0; oi < num_order.size(); ++oi) {
+        const int bb = num_order[oi];
         const int64_t nr = P->num_counts[bb];
-        const int32_t* rows = lists + off;
-        off += nr;
+        const int32_t* rows = lists + bin_off[bb];
         if (nr == 0 || bb == BIN_EMPTY) continue;
+        use_stream(P, (int)oi);
         if (bb == BIN_TINY) {
             SPG_TRY(launch(P, "num_tiny", [&] {
-                k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, ab, crp, ccol, cval);
+                k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, crp, ccol, cval);
             }));
         } else if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "num_small", [&] {
-                k_num_small<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval);
+                k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval);
             }));
         } else if (bb >= BIN_RANK0) {
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
             const int64_t cap = 4096ll << (bb - BIN_RANK0);
             const size_t lds = (size_t)nwords * 8 + (size_t)cap * sizeof(typename Sr<SR>::acc_t);
-            SPG_TRY(launch(P, "num_rank" + std::to_string(cap), [&] {
-                k_num_rank<SR, 512><<<(unsigned)nr, 512, lds, P->stream>>>(
-                    a, b, rows, ab, ae, P->bm_save.as<uint32_t>(), P->heavy_idx.as<int32_t>(), nwords, crp, ccol,
-                    cval);
+            SPG_TRY(with_gm(P, [&](auto gm) {
+                return launch(P, "num_rank" + std::to_string(cap), [&] {
+                    k_num_rank<SR, 512, decltype(gm)::value><<<(unsigned)nr, 512, lds, cs(P)>>>(
+                        a, b, rows, ab, ae, P->bm_save.as<uint32_t>(), P->heavy_idx.as<int32_t>(), nwords, crp, ccol,
+                        cval);
+                });
             }));
         } else if (bb == BIN_DENSE || bb == BIN_DENSE_PAR) {
             const bool par = bb == BIN_DENSE_PAR;
@@ -608,7 +740,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                     if (entries > 0) {
                         int32_t* sp = P->split.as<int32_t>();
                         SPG_TRY(launch(P, "split_table", [&] {
-                            k_split_table<<<grid_for(entries, 256), 256, 0, P->stream>>>(b, W, chunks, sp);
+                            k_split_table<<<grid_for(entries, 256), 256, 0, cs(P)>>>(b, W, chunks, sp);
                         }));
                     }
                     split_built = true;
@@ -617,40 +749,46 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             }
             const int32_t* cc = P->chunk_save.as<int32_t>();
             const int32_t* hi = P->heavy_idx.as<int32_t>();
-            const unsigned grid = (unsigned)(par ? nr * chunks : nr);
+            const unsigned grid = (unsigned)std::min<int64_t>(par ? nr * chunks : nr, 1 << 16);
             const std::string name = par ? "num_dense_par" : "num_dense";
+            SPG_TRY(with_gm(P, [&](auto gm) -> spg_status {
+                constexpr int GM = decltype(gm)::value;
             if (W == 16384) {
                 SPG_TRY(launch(P, name, [&] {
                     if (par)
-                        k_num_dense<SR, 1024, 16384, true><<<grid, 1024, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                        k_num_dense<SR, 1024, 16384, true, GM><<<grid, 1024, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                     else
-                        k_num_dense<SR, 1024, 16384, false><<<grid, 1024, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                        k_num_dense<SR, 1024, 16384, false, GM><<<grid, 1024, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
             } else if (W == 8192) {
                 SPG_TRY(launch(P, name, [&] {
                     if (par)
-                        k_num_dense<SR, 512, 8192, true><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                        k_num_dense<SR, 512, 8192, true, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                     else
-                        k_num_dense<SR, 512, 8192, false><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                        k_num_dense<SR, 512, 8192, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
             } else {
                 SPG_TRY(launch(P, name, [&] {
                     if (par)
-                        k_num_dense<SR, 512, 4096, true><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                        k_num_dense<SR, 512, 4096, true, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                     else
-                        k_num_dense<SR, 512, 4096, false><<<grid, 512, 0, P->stream>>>(a, b, rows, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                        k_num_dense<SR, 512, 4096, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
             }
+                return SPG_OK;
+            }));
         } else {
             SPG_TRY(num_hash_dispatch<SR>(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, crp, ccol, cval));
         }
     }
+    SPG_TRY(join_streams(P));
     return SPG_OK;
 }
 
 extern "C" spg_status spgemm_numeric(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B,
                                      int64_t k_lo, int64_t k_hi, const int64_t* c_row_ptr, int32_t* c_col,
                                      void* c_val) {
+    if (P) P->cur = nullptr;
     if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
     if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
     SPG_TRY(check_csr(A, "A", sr, c_val != nullptr));
@@ -697,15 +835,15 @@ static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, c
         if (nr == 0 || bb == MBIN_EMPTY) continue;
         if (bb == MBIN_SMALL) {
             SPG_TRY(launch(P, "merge_small", [&] {
-                k_merge_small<SR><<<grid_for(nr, 4), 256, 0, P->stream>>>(c, d, rows, (int32_t)nr, cnt, orp, ocol, oval);
+                k_merge_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, d, rows, (int32_t)nr, cnt, orp, ocol, oval);
             }));
         } else if (bb == MBIN_LDS) {
             SPG_TRY(launch(P, "merge_lds", [&] {
-                k_merge_lds<SR, 256><<<(unsigned)nr, 256, 0, P->stream>>>(c, d, rows, tl, cnt, orp, ocol, oval);
+                k_merge_lds<SR, 256><<<(unsigned)nr, 256, 0, cs(P)>>>(c, d, rows, tl, cnt, orp, ocol, oval);
             }));
         } else {
             SPG_TRY(launch(P, "merge_dense", [&] {
-                k_merge_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, P->stream>>>(c, d, rows, n, cnt, orp, ocol, oval);
+                k_merge_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, cs(P)>>>(c, d, rows, n, cnt, orp, ocol, oval);
             }));
         }
     }
@@ -714,12 +852,14 @@ static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, c
 
 extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t nlayers, const spg_csr* layers,
                                           int64_t* out_row_ptr, int32_t* out_col, void* out_val, int64_t* out_nnz) {
+    if (P) P->cur = nullptr;
     if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
     if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
     if (nlayers < 1 || nlayers > 64) return fail(SPG_ERR_ARG, "nlayers must be in [1, 64]");
     if (!layers || !out_row_ptr) return fail(SPG_ERR_ARG, "layers or out_row_ptr is NULL");
     const bool count_pass = out_col == nullptr;
     const int64_t m = layers[0].nrows, n = layers[0].ncols;
+    if (m > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split by rows");
     for (int l = 0; l < nlayers; ++l) {
         SPG_TRY(check_csr(&layers[l], "layer", sr, !count_pass && out_val != nullptr));
         if (layers[l].nrows != m || layers[l].ncols != n) return fail(SPG_ERR_SHAPE, "layer shapes differ");
@@ -753,12 +893,12 @@ extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t n
         SPG_TRY(fill_i32(P, ctr, NBINS, 0));
         if (m > 0) {
             SPG_TRY(launch(P, "merge_rowinfo", [&] {
-                k_merge_rowinfo<<<grid_for(m, 256), 256, 0, P->stream>>>(m, nlayers, P->layer_desc.as<LayerDesc>(),
+                k_merge_rowinfo<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, nlayers, P->layer_desc.as<LayerDesc>(),
                                                                         P->merge_len.as<int64_t>(), P->mbin.as<uint8_t>(),
                                                                         stats);
             }));
             SPG_TRY(launch(P, "bin_scatter", [&] {
-                k_bin_scatter<<<grid_for(m, 256), 256, 0, P->stream>>>(m, P->mbin.as<uint8_t>(), stats, ctr,
+                k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->mbin.as<uint8_t>(), stats, ctr,
                                                                        P->mlists.as<int32_t>());
             }));
         }

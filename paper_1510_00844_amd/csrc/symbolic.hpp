@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* ro
 // The finished bitmap is the row's stored set; it is written to bm_save
 // (slot = position in the bin list, recorded in heavy_idx) so the numeric
 // pass can place values by rank without gathering the columns again.
-template <int NT>
+template <int NT, int GM>
 __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* rows,
                                                    const int64_t* a_beg, const int64_t* a_end,
                                                    int64_t* cnt, int32_t nwords, uint32_t* bm_save,
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
     for (int t = threadIdx.x; t < nwords; t += NT) bm[t] = 0u;
     for (int t = threadIdx.x; t < MAX_CHUNKS; t += NT) s_chunk[t] = 0;
     __syncthreads();
-    for_each_product_u<NT, 8>(
+    for_each_product_gm<NT, GM>(
         a_beg[i], a_end[i], L,
         [&](int64_t p, int64_t& bs, int32_t& len) {
             int64_t k = A.col[p];

@@ -267,6 +267,24 @@ def test_errors(plan):
     vplan.close()
 
 
+@pytest.mark.parametrize("cols", [4096, 8192, 16384])
+def test_rmat_s19_c5_chunk_widths(cols):
+    """C5 shape with every dense chunk width: with 4096 columns a row has
+    128 chunks and the (row, chunk) work items exceed what one grid can hold,
+    so the kernel must stride over them."""
+    A = synth.rmat(19, 16, synth.G500, seed=6)
+    p = spg.Plan(dense_chunk_cols=cols)
+    C = run(p, "f64", A, A)
+    st = p.stats()
+    assert st["num_rows"][11] > 0 and st["num_rows"][12] > 0
+    f = oracle.row_flops(A, A)
+    rows = np.argsort(-f)[:60]
+    check_rows_vs_oracle(C, A, A, "f64", rows)
+    del C
+    p.close()
+    torch.cuda.empty_cache()
+
+
 def test_rmat_s19_c5_sampled(plan):
     """C5 shape (R-MAT G500 scale 19): sampled rows, including the hub rows
     with millions of products, against the oracle."""
