@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--unroll", type=int, default=0, help="gathers in flight per lane (4 or 8)")
     ap.add_argument("--sym-gather-map", type=int, default=0)
     ap.add_argument("--sym-unroll", type=int, default=0)
+    ap.add_argument("--no-c5", action="store_true", help="skip the scale-19 learned-sizing comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (3 times), the reference for "
                          "scaling the HBM byte counters")
@@ -103,6 +104,66 @@ def model_bytes(m, annz, flops, cnnz, sr):
     + 8(m+1) + nnzC(4+w)."""
     w = value_width(sr)
     return 8.0 * (m + 1) * 2 + annz * (4 + w) + 16.0 * annz + flops * (4 + w) + cnnz * (4 + w)
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, r
+
+
+def learned_modes(A2, dA2, args):
+    """Single-pass product with the trained predictor against the two-phase
+    product and against single-pass sizing without a predictor (capacity =
+    min(flops, n)): C2 and the R-MAT G500 scale-19 product."""
+    import paper_1510_00844_amd as spg
+    import synth
+    from paper_1510_00844_amd import learned
+    res = {}
+    if not os.path.exists(learned.WEIGHTS):
+        return res
+    params = learned.load()
+    cases = [("c2", A2, dA2)]
+    if not args.no_c5:
+        A5 = synth.rmat(19, 16, synth.G500, seed=6)
+        cases.append(("c5", A5, spg.DeviceCSR.from_arrays(A5.nrows, A5.ncols, A5.row_ptr, A5.col, A5.val)))
+    for name, A, dA in cases:
+        plan = spg.Plan()
+
+        def plain():
+            rp, nnz = spg.spgemm_symbolic(plan, "f64", dA, dA)
+            spg.spgemm_numeric(plan, "f64", dA, dA, rp, nnz)
+            return nnz
+
+        def single(p):
+            def f():
+                nnz, st = spg.spgemm_learned_run(plan, "f64", dA, dA, p, 0.15)
+                spg.spgemm_learned_fetch(plan, "f64", dA, dA, nnz)
+                return nnz, st
+            return f
+
+        reps = 3
+        t_plain, nnz = _time(plain, reps)
+        flops = plan.stats()["flops"]
+        t_l, (nnz_l, st_l) = _time(single(params), reps)
+        t_u, (nnz_u, st_u) = _time(single(None), reps)
+        assert nnz_l == nnz == nnz_u
+        g = lambda t: round(2.0 * flops / (t * 1e-3) / 1e9, 3)
+        res[name + "_plain"] = {"ms": round(t_plain, 4), "gflops": g(t_plain), "flops": flops, "nnz_c": nnz}
+        res[name + "_learned"] = {"ms": round(t_l, 4), "gflops": g(t_l), "speedup_vs_plain": round(t_plain / t_l, 3),
+                                  "stats": {k: v for k, v in st_l.items() if k != "bin_rows"}}
+        res[name + "_upper_bound_sizing"] = {"ms": round(t_u, 4), "gflops": g(t_u),
+                                             "stats": {k: v for k, v in st_u.items() if k != "bin_rows"}}
+        plan.close()
+        del dA
+        import torch
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -210,6 +271,7 @@ def main():
                                    "gflops": round(2.0 * flops / (xms * 1e-3) / 1e9, 3),
                                    "hbm_model_gbs": round(model_bytes(A.nrows, A.nnz, flops, n2, xsr) / (xms * 1e-3) / 1e9, 2)}
             p2.close()
+        extras.update(learned_modes(A, dA, args))
         out["modes"] = extras
     if not args.no_cpu_baseline:
         import oracle

@@ -163,6 +163,68 @@ typedef struct {
 spg_status spg_profile_read(spg_plan plan, spg_kernel_time* out, int32_t cap, int32_t* n);
 spg_status spg_profile_reset(spg_plan plan);
 
+/* ------------------------------------------------------------------------
+ * Row-size predictor (not in the paper; its Section 3 notes that computing
+ * the output structure up front is about as hard as the product itself).
+ * A 3-32-32-1 ReLU network in FP32 maps (log1p nnz(A(i,:)), log1p flops_i,
+ * log1p max_k nnz(B(k,:))) to an estimate of log1p nnz(C(i,:)).  Parameters:
+ * SPG_MLP_NPARAMS floats on the device, in the order W1[32][3] (row-major),
+ * b1[32], W2[32][32], b2[32], w3[32], b3.
+ * ------------------------------------------------------------------------ */
+#define SPG_MLP_NPARAMS 1217
+
+/* y[i] = network(x[3i..3i+2]) for i < n.  All pointers device. */
+spg_status spg_mlp_forward(spg_plan plan, const float* params, const float* x, int64_t n, float* y);
+
+/* Adds to grad[SPG_MLP_NPARAMS] the gradient of (1/n) sum_i a_i (y_i - t_i)^2,
+ * a_i = alpha where y_i < t_i else 1, and adds the loss to *loss (if not
+ * NULL).  The caller zeroes grad/loss first.  Device pointers. */
+spg_status spg_mlp_grad(spg_plan plan, const float* params, const float* x, const float* t, int64_t n,
+                        float alpha, float* grad, float* loss);
+
+/* One Adam step (bias-corrected; step counts from 1) on params, with
+ * moment buffers m, v of SPG_MLP_NPARAMS floats; grad is cleared to zero
+ * afterwards.  Device pointers. */
+spg_status spg_mlp_adam(spg_plan plan, float* params, float* grad, float* m, float* v, int64_t step,
+                        float lr, float beta1, float beta2, float eps);
+
+/* Training data from the last spgemm_symbolic on this plan: for every row
+ * whose size would be predicted (more than one A entry, more products than
+ * small_max_flops) and that has at least min_flops products, its features
+ * (x, 3 floats) and target log1p of its exact count from c_row_ptr (t).  x
+ * and t are device arrays of at least 3m and m floats; *nsel (host)
+ * receives the number of rows written (order unspecified).  Synchronizes. */
+spg_status spg_row_training_data(spg_plan plan, const int64_t* c_row_ptr, int64_t min_flops, float* x, float* t,
+                                 int64_t* nsel);
+
+typedef struct {
+    int64_t rows_predicted; /* rows given a predicted capacity */
+    int64_t rows_exact;     /* rows too large for a single-pass accumulator: exact method */
+    int64_t rows_overflow;  /* predicted rows whose count exceeded the capacity: redone exactly */
+    int64_t slots;          /* padded entries allocated */
+    int64_t nnz_c;
+    int64_t nnz_single;     /* entries of C produced by the single pass (the rest by the exact method) */
+    int64_t bin_rows[SPG_NBINS];
+} spg_learned_stats;
+
+/* Single-pass product with predicted row sizes: C = A(:,K) B(K,:) computed
+ * into plan-owned padded slots of capacity clamp((1 + margin) * prediction
+ * + 8, max_k nnz(B(k,:)), min(flops_i, n)); mlp_params (device) NULL means
+ * capacity = min(flops_i, n), the bound without a predictor.  Rows whose
+ * count exceeds their slot, and rows too large for a single-pass
+ * accumulator, are computed by the exact two-phase method.  *c_nnz (host)
+ * receives nnz(C); st (host, optional) the statistics.  Synchronizes. */
+spg_status spgemm_learned_run(spg_plan plan, spg_semiring sr, const spg_csr* A, const spg_csr* B,
+                              int64_t k_lo, int64_t k_hi, const float* mlp_params, float margin,
+                              int64_t* c_nnz, spg_learned_stats* st);
+
+/* Writes the result of the last spgemm_learned_run (same A and B) as
+ * canonical CSR into caller-owned device arrays: c_row_ptr (m+1), c_col and
+ * c_val (nnz(C) entries; c_val may be NULL).  The structure is identical to
+ * the two-phase method's. */
+spg_status spgemm_learned_fetch(spg_plan plan, const spg_csr* A, const spg_csr* B, int64_t* c_row_ptr,
+                                int32_t* c_col, void* c_val);
+
 const char* spg_status_string(spg_status s);
 const char* spg_last_error(void);
 

@@ -58,6 +58,15 @@ class Stats(ctypes.Structure):
                 ("dense_chunk_cols", ctypes.c_int32), ("dense_chunks", ctypes.c_int32)]
 
 
+MLP_NPARAMS = 1217
+
+
+class LearnedStats(ctypes.Structure):
+    _fields_ = [("rows_predicted", ctypes.c_int64), ("rows_exact", ctypes.c_int64),
+                ("rows_overflow", ctypes.c_int64), ("slots", ctypes.c_int64), ("nnz_c", ctypes.c_int64),
+                ("nnz_single", ctypes.c_int64), ("bin_rows", ctypes.c_int64 * NBINS)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
@@ -86,6 +95,14 @@ def lib():
             "spg_plan_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
             "spg_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], ctypes.c_int),
             "spg_profile_reset": ([P], ctypes.c_int),
+            "spg_mlp_forward": ([P, P, P, I64, P], ctypes.c_int),
+            "spg_mlp_grad": ([P, P, P, P, I64, ctypes.c_float, P, P], ctypes.c_int),
+            "spg_mlp_adam": ([P, P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
+                             ctypes.c_int),
+            "spg_row_training_data": ([P, P, I64, P, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "spgemm_learned_run": ([P, ctypes.c_int, CP, CP, I64, I64, P, ctypes.c_float, ctypes.POINTER(I64),
+                                    ctypes.POINTER(LearnedStats)], ctypes.c_int),
+            "spgemm_learned_fetch": ([P, CP, CP, P, P, P], ctypes.c_int),
             "spg_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "spg_last_error": ([], ctypes.c_char_p),
         }
@@ -250,3 +267,62 @@ def spgemm_merge_layers(plan: Plan, sr: str, layers: Sequence[DeviceCSR], values
                                          ctypes.c_void_p(col.data_ptr()),
                                          ctypes.c_void_p(val.data_ptr()) if values else None, None))
     return DeviceCSR(m, n, rp, col, val)
+
+
+def _vp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def spg_mlp_forward(plan: Plan, params: torch.Tensor, x: torch.Tensor, y: torch.Tensor):
+    _check(lib().spg_mlp_forward(plan.handle, _vp(params), _vp(x), x.shape[0], _vp(y)))
+
+
+def spg_mlp_grad(plan: Plan, params, x, t, alpha: float, grad, loss=None):
+    _check(lib().spg_mlp_grad(plan.handle, _vp(params), _vp(x), _vp(t), t.shape[0], float(alpha), _vp(grad),
+                              _vp(loss)))
+
+
+def spg_mlp_adam(plan: Plan, params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().spg_mlp_adam(plan.handle, _vp(params), _vp(grad), _vp(m), _vp(v), int(step), float(lr),
+                              float(beta1), float(beta2), float(eps)))
+
+
+def spg_row_training_data(plan: Plan, c_row_ptr: torch.Tensor, m: int, min_flops: int = 0):
+    """Features (n, 3) and targets (n,) of the predicted rows (with at least
+    min_flops products) of the last symbolic call."""
+    x = torch.empty(max(m, 1) * 3, dtype=torch.float32, device=plan.device)
+    t = torch.empty(max(m, 1), dtype=torch.float32, device=plan.device)
+    n = ctypes.c_int64()
+    _check(lib().spg_row_training_data(plan.handle, _vp(c_row_ptr), int(min_flops), _vp(x), _vp(t),
+                                       ctypes.byref(n)))
+    return x[: 3 * n.value].view(n.value, 3), t[: n.value]
+
+
+def spgemm_learned_run(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, params: Optional[torch.Tensor],
+                       margin: float = 0.15, k_lo=None, k_hi=None):
+    """Single-pass product with predicted row sizes; returns (nnz, stats)."""
+    k_lo, k_hi = _window(A, k_lo, k_hi)
+    a, b = A._c(sr), B._c(sr)
+    nnz = ctypes.c_int64()
+    st = LearnedStats()
+    _check(lib().spgemm_learned_run(plan.handle, SEMIRINGS[sr], ctypes.byref(a), ctypes.byref(b), k_lo, k_hi,
+                                    _vp(params), float(margin), ctypes.byref(nnz), ctypes.byref(st)))
+    stats = {k: getattr(st, k) for k in ("rows_predicted", "rows_exact", "rows_overflow", "slots", "nnz_c",
+                                         "nnz_single")}
+    stats["bin_rows"] = list(st.bin_rows)
+    return nnz.value, stats
+
+
+def spgemm_learned_fetch(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, nnz: int, values=True) -> DeviceCSR:
+    a, b = A._c(sr), B._c(sr)
+    rp = torch.empty(A.nrows + 1, dtype=torch.int64, device=plan.device)
+    col = torch.empty(max(nnz, 0), dtype=torch.int32, device=plan.device)
+    val = torch.empty(max(nnz, 0), dtype=TORCH_DTYPE[sr], device=plan.device) if values else None
+    _check(lib().spgemm_learned_fetch(plan.handle, ctypes.byref(a), ctypes.byref(b), _vp(rp),
+                                      _vp(col) if nnz > 0 else None, _vp(val) if (values and nnz > 0) else None))
+    return DeviceCSR(A.nrows, B.ncols, rp, col, val)
+
+
+def spgemm_learned(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, params, margin=0.15, k_lo=None, k_hi=None):
+    nnz, st = spgemm_learned_run(plan, sr, A, B, params, margin, k_lo, k_hi)
+    return spgemm_learned_fetch(plan, sr, A, B, nnz), st

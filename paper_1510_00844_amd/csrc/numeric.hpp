@@ -19,6 +19,7 @@
 //          the bitmap scan emits columns in order, so no sort is needed.
 #pragma once
 #include "products.hpp"
+#include "rowinfo.hpp"
 #include "symbolic.hpp"
 
 namespace spg {
@@ -49,10 +50,12 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
     }
 }
 
+// cnt_out (optional) receives each row's output count.
 template <int SR>
 __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
                                                    const int64_t* a_beg, const int64_t* a_end,
-                                                   const int64_t* c_rp, int32_t* c_col, void* c_val) {
+                                                   const int64_t* c_rp, int32_t* c_col, void* c_val,
+                                                   int64_t* cnt_out) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -90,12 +93,17 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
         c_col[o] = (int32_t)col;
         if (c_val) S::store(c_val, o, acc);
     }
+    if (cnt_out && lane == 0) cnt_out[i] = __popcll(heads);
 }
 
+// cnt_out (optional) receives each row's output count; a count above the
+// slot c_rp[i+1]-c_rp[i] means the slot overflowed (only then is the output
+// incomplete).
 template <int SR, int NT, int LOG2T>
 __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* rows,
                                                  const int64_t* a_beg, const int64_t* a_end,
-                                                 const int64_t* c_rp, int32_t* c_col, void* c_val) {
+                                                 const int64_t* c_rp, int32_t* c_col, void* c_val,
+                                                 int64_t* cnt_out) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
     constexpr int T = 1 << LOG2T;
@@ -157,6 +165,8 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     int32_t pos = block_exclusive_scan<NT, int32_t>(mine, &cnt, red);
     const int64_t o = c_rp[i];
     const int32_t cnt_sym = (int32_t)(c_rp[i + 1] - o);
+    if (cnt_out && threadIdx.x == 0) cnt_out[i] = cnt;
+    if (cnt_out && cnt > cnt_sym) return;  // slot overflow: the row is redone exactly
     // Output order.  When the row's columns span few enough bitmap words, the
     // rank of a column is the popcount of the bitmap below it (prefix of
     // per-word popcounts): no sort.  Otherwise sort (column, slot) keys.
@@ -416,6 +426,116 @@ __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* ro
         });
     if (c_val)
         for (int r = threadIdx.x; r < cnt; r += NT) S::store(c_val, off + r, acc[r]);
+}
+
+// Rank chunks: the rows of the bitmap pass that are too large for the
+// per-row rank kernel.  A row's column chunks of W columns (counts recorded
+// by the bitmap pass) are grouped greedily into items of at most RC outputs
+// and at most G chunks; an item accumulates in LDS at index = rank inside
+// the item, with its B segments taken from the split table.
+struct RankItem {
+    int32_t r;      // index into the bin's row list
+    int32_t c0, c1; // chunk range [c0, c1)
+    int32_t cnt;    // outputs of the item
+    int64_t roff;   // outputs of the row before the item
+};
+
+__global__ void __launch_bounds__(256) k_rank_items(const int32_t* rows, int32_t nrows, const int32_t* heavy_idx,
+                                                    const int32_t* chunk_cnt, int32_t P, int32_t RC, int32_t G,
+                                                    RankItem* items, int32_t* nitems) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= nrows) return;
+    const int32_t* cc = chunk_cnt + (int64_t)heavy_idx[rows[r]] * P;
+    int64_t roff = 0;
+    int c0 = 0;
+    while (c0 < P) {
+        int c1 = c0;
+        int32_t n = 0;
+        while (c1 < P && c1 - c0 < G && n + cc[c1] <= RC) n += cc[c1++];
+        if (c1 == c0) {  // a chunk above RC (the host keeps RC >= W): take it alone, always progress
+            n = cc[c0];
+            c1 = c0 + 1;
+        }
+        if (n > 0) {
+            const int slot = atomicAdd(nitems, 1);
+            items[slot] = RankItem{r, c0, c1, n, roff};
+        }
+        roff += n;
+        c0 = c1;
+    }
+}
+
+// Dynamic LDS: G*W/32 packed words (prefix << 32 | bits), then RC values.
+template <int SR, int NT, int GM>
+__global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const int32_t* rows, const int64_t* a_beg,
+                                                  const int64_t* a_end, const uint32_t* bm_save,
+                                                  const int32_t* heavy_idx, int32_t nwords, const int32_t* split,
+                                                  int32_t P, const RankItem* items, const int32_t* nitems,
+                                                  int32_t RC, int32_t G, const int64_t* c_rp, int32_t* c_col,
+                                                  void* c_val) {
+    typedef Sr<SR> S;
+    typedef typename S::acc_t V;
+    const int WPC = W / 32;  // bitmap words per chunk
+    extern __shared__ uint64_t dyn[];
+    uint64_t* bw = dyn;
+    V* acc = reinterpret_cast<V*>(dyn + (int64_t)G * WPC);
+    __shared__ V s_av[NT];
+    __shared__ ProductLds<NT> L;
+    __shared__ int32_t red[NT / SPG_WAVE + 1];
+    for (int t = threadIdx.x; t < RC; t += NT) acc[t] = S::zero();
+    __syncthreads();
+    const int32_t total_items = *nitems;
+    for (int32_t it = blockIdx.x; it < total_items; it += gridDim.x) {
+        const RankItem item = items[it];
+        const int64_t i = rows[item.r];
+        const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords + (int64_t)item.c0 * WPC;
+        const int nw = (item.c1 - item.c0) * WPC;
+        const int64_t off = c_rp[i] + item.roff;
+        const int32_t cbase = item.c0 * W;
+        // packed words and columns, one contiguous run of words per thread
+        const int wpt = (nw + NT - 1) / NT;
+        const int w0 = threadIdx.x * wpt;
+        const int w1 = w0 + wpt < nw ? w0 + wpt : nw;
+        int32_t part = 0;
+        for (int w = w0; w < w1; ++w) part += __popc(src[w]);
+        int32_t dummy;
+        int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
+        for (int w = w0; w < w1; ++w) {
+            uint32_t bits = src[w];
+            bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                if (run < item.cnt) c_col[off + run] = cbase + w * 32 + b;
+                ++run;
+            }
+        }
+        __syncthreads();
+        const int c0 = item.c0, c1 = item.c1;
+        for_each_product_gm<NT, GM>(
+            a_beg[i], a_end[i], L,
+            [&](int64_t p, int64_t& bs, int32_t& len) {
+                const int64_t k = A.col[p];
+                const int32_t* sp = split + k * (P + 1);
+                const int64_t rs = B.rp[k];
+                bs = rs + sp[c0];
+                len = sp[c1] - sp[c0];
+            },
+            [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
+            [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
+            [&](int t, const BEntry<V>& x) {
+                const uint32_t j = (uint32_t)(x.col - cbase);
+                const uint64_t wd = bw[j >> 5];
+                const int32_t rank = (int32_t)(wd >> 32) + __popc((uint32_t)wd & ((1u << (j & 31)) - 1u));
+                if (rank < RC) S::lds_add(&acc[rank], S::mul(s_av[t], x.val));
+            });
+        const int32_t nout = item.cnt < RC ? item.cnt : RC;
+        for (int r = threadIdx.x; r < nout; r += NT) {
+            if (c_val) S::store(c_val, off + r, acc[r]);
+            acc[r] = S::zero();
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace spg

@@ -43,7 +43,7 @@ __device__ inline int sym_bin(int64_t flops, int64_t annz, const BinParams& bp) 
     // a bitmap over all n columns costs n/32 words to clear and count; use it
     // once the row's products outnumber that, or once a hash table would not fit
     bool bitmap_cheaper = bp.dense_ok && flops * 32 >= bp.ncols;
-    if (flops <= bp.hash_max_flops && !bitmap_cheaper) {
+    if (flops <= bp.hash_max_flops && !bitmap_cheaper) {  // larger rows: bitmap, in blocks if n is large
         int lg = ceil_log2_i64(2 * flops);
         if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
         return BIN_HASH0 + (lg - HASH_MIN_LOG2);
@@ -64,12 +64,16 @@ __device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, bool sym
         if (lg < RANK_MIN_LOG2) lg = RANK_MIN_LOG2;
         return BIN_RANK0 + (lg - RANK_MIN_LOG2);
     }
-    if (cnt <= bp.hash_max_nnz) {
+    // rows with a saved bitmap take its rank chunks once a hash table would
+    // need the largest size (one workgroup per CU)
+    const bool chunks_ok = sym_dense && bp.chunk_counts;
+    const int64_t hash_lim = chunks_ok && bp.hash_max_nnz > 2048 ? 2048 : bp.hash_max_nnz;
+    if (cnt <= hash_lim) {
         int lg = ceil_log2_i64(2 * cnt);
         if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
         return BIN_HASH0 + (lg - HASH_MIN_LOG2);
     }
-    return (sym_dense && bp.chunk_counts) ? BIN_DENSE_PAR : BIN_DENSE;
+    return chunks_ok ? BIN_DENSE_PAR : BIN_DENSE;
 }
 
 struct RowInfoOut {

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/spgemm.h"
+#include "learned.hpp"
 #include "merge.hpp"
 #include "numeric.hpp"
 #include "rowinfo.hpp"
@@ -99,7 +100,7 @@ struct spg_plan_s {
 
     // per-row state of the current product
     DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
-    DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save;
+    DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save, rank_items;
     int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
     LayerDesc* h_layers = nullptr; // pinned staging for merge descriptors
     int h_layers_cap = 0;
@@ -111,6 +112,15 @@ struct spg_plan_s {
     int64_t num_counts[4 * NBINS];
     int64_t last_flops = 0, last_nnz = -1;
     int dense_chunks = 0;
+
+    // single-pass (predicted sizes) state
+    DevBuf lcap, lcnt, slot, pcol, pval, fb_list, fb_redo, sub_rp, sub_col, sub_val, sub_crp, sub_ccol, sub_cval, mlp_tmp;
+    spg_plan sub = nullptr;  // plan of the exact method for the rows it must redo
+    Signature lsig;
+    bool have_learned = false;
+    int64_t l_counts[2 * NBINS];
+    int64_t l_nfb = 0, l_nexact = 0, l_slots = 0, l_nnz = 0, l_sub_nnz = 0, l_sub_annz = 0;
+    spg_semiring l_sr = SPG_SR_PLUS_TIMES_F64;
 
     // merge state
     std::vector<LayerDesc> merge_sig;
@@ -193,6 +203,8 @@ static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per
 
 // static LDS of k_num_rank<*, 512> (A values, product offsets, scan scratch), with margin
 static const int RANK_STATIC_LDS = (int)(8 * 512 + sizeof(ProductLds<512>) + 4 * 16 + 256);
+// rank-chunk items: at most this many outputs and this many column chunks
+static const int RANKC_CAP = 4096;
 
 // ---------------------------------------------------------------------------
 // public helpers
@@ -202,8 +214,8 @@ extern "C" void spg_default_opts(spg_opts* o) {
     std::memset(o, 0, sizeof(*o));
     o->validate = 0;
     o->small_max_flops = 64;
-    o->hash_max_flops = 8192;
-    o->hash_max_nnz = 2048;
+    o->hash_max_flops = 4096;
+    o->hash_max_nnz = 4096;
     o->dense_chunk_cols = 8192;
     o->profile = 0;
     o->streams = 4;
@@ -239,6 +251,12 @@ static void set_lds_attributes(spg_plan P) {
     hipFuncSetAttribute((const void*)k_num_rank<SR_F64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
     hipFuncSetAttribute((const void*)k_num_rank<SR_I64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
     hipFuncSetAttribute((const void*)k_num_rank<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rankc<SR_F64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rankc<SR_I64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rankc<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_learned_fused<SR_F64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_learned_fused<SR_I64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_learned_fused<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
 }
 
 static int gather_mode(int map, int unroll) { return (map == 2 ? 2 : 0) + (unroll == 8 ? 1 : 0); }
@@ -291,9 +309,9 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_flops must be in [1, 8192]");
     }
-    if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 2048) {
+    if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 4096) {
         delete P;
-        return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 2048]");
+        return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
     }
     if (P->opts.dense_chunk_cols != 16384 && P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096) {
         delete P;
@@ -340,8 +358,11 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
     hipStreamSynchronize(P->stream);
     for (DevBuf* b : {&P->a_beg, &P->a_end, &P->flops, &P->maxb, &P->bin, &P->lists, &P->long_rows,
                       &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
-                      &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save})
+                      &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save, &P->rank_items,
+                      &P->lcap, &P->lcnt, &P->slot, &P->pcol, &P->pval, &P->fb_list, &P->fb_redo, &P->sub_rp,
+                      &P->sub_col, &P->sub_val, &P->sub_crp, &P->sub_ccol, &P->sub_cval, &P->mlp_tmp})
         b->release();
+    if (P->sub) spg_plan_destroy(P->sub);
     if (P->h_stats) hipHostFree(P->h_stats);
     if (P->h_layers) hipHostFree(P->h_layers);
     for (auto& r : P->prof_pending) {
@@ -473,6 +494,8 @@ static BinParams bin_params(spg_plan P, int64_t n) {
     bp.hash_max_flops = P->opts.hash_max_flops;
     bp.hash_max_nnz = P->opts.hash_max_nnz;
     const int64_t bitmap_bytes = ((n + 31) / 32) * 4;
+    // dense_ok: one LDS bitmap covers all n columns (the bitmap pass then
+    // counts in one block and can save the bitmap for the numeric pass)
     bp.dense_ok = (n <= (1 << 19)) && (bitmap_bytes + (int64_t)sizeof(ProductLds<512>) + 256 <= P->max_lds);
     bp.ncols = n;
     // the bitmap pass records per-chunk counts of the numeric column chunks
@@ -565,8 +588,6 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     int64_t tot = 0;
     for (int x = 0; x < NBINS; ++x) tot += P->sym_counts[NBINS + x];
     P->last_flops = tot;
-    if (P->sym_counts[BIN_DENSE] > 0 && !bp.dense_ok)
-        return fail(SPG_ERR_INDEX_RANGE, "rows with more products than the hash limit need n <= 2^19 columns");
 
     // per-bin accumulators, independent bins on separate streams
     const int32_t* lists = P->lists.as<int32_t>();
@@ -587,21 +608,21 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                                                                      P->a_end.as<int64_t>(), cnt);
             }));
         } else if (bb == BIN_DENSE) {
-            const int32_t nwords = (int32_t)((n + 31) / 32);
+            const int32_t nwords = (int32_t)std::min<int64_t>((n + 31) / 32, 1 << 14);
             uint32_t* save = nullptr;
             int32_t* hidx = nullptr;
             int32_t* csave = nullptr;
             const int32_t W = P->opts.dense_chunk_cols;
             const int32_t nchunks = (int32_t)((n + W - 1) / W);
-            if (bp.rank_max_log2 || bp.chunk_counts) {
+            if (bp.dense_ok && (bp.rank_max_log2 || bp.chunk_counts)) {
                 SPG_TRY(P->heavy_idx.ensure(4 * (size_t)std::max<int64_t>(m, 1), "bitmap slots"));
                 hidx = P->heavy_idx.as<int32_t>();
             }
-            if (bp.rank_max_log2) {
+            if (bp.dense_ok && (bp.rank_max_log2 || bp.chunk_counts)) {
                 SPG_TRY(P->bm_save.ensure((size_t)nr * nwords * 4, "row bitmaps"));
                 save = P->bm_save.as<uint32_t>();
             }
-            if (bp.chunk_counts) {
+            if (bp.dense_ok && bp.chunk_counts) {
                 SPG_TRY(P->chunk_save.ensure((size_t)nr * nchunks * 4, "chunk counts"));
                 csave = P->chunk_save.as<int32_t>();
             }
@@ -656,24 +677,25 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
 // ---------------------------------------------------------------------------
 template <int SR, int NT, int LOG2T>
 static spg_status launch_num_hash(spg_plan P, Csr A, Csr B, const int32_t* rows, int64_t nr,
-                                  const int64_t* crp, int32_t* ccol, void* cval) {
+                                  const int64_t* crp, int32_t* ccol, void* cval, int64_t* cnt_out) {
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
     return launch(P, "num_hash" + std::to_string(1 << LOG2T), [&] {
-        k_num_hash<SR, NT, LOG2T><<<(unsigned)nr, NT, 0, cs(P)>>>(A, B, rows, ab, ae, crp, ccol, cval);
+        k_num_hash<SR, NT, LOG2T><<<(unsigned)nr, NT, 0, cs(P)>>>(A, B, rows, ab, ae, crp, ccol, cval, cnt_out);
     });
 }
 
 template <int SR>
 static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int32_t* rows, int64_t nr,
-                                    const int64_t* crp, int32_t* ccol, void* cval) {
+                                    const int64_t* crp, int32_t* ccol, void* cval, int64_t* cnt_out = nullptr) {
     switch (lg) {
-        case 7: return launch_num_hash<SR, 64, 7>(P, A, B, rows, nr, crp, ccol, cval);
-        case 8: return launch_num_hash<SR, 64, 8>(P, A, B, rows, nr, crp, ccol, cval);
-        case 9: return launch_num_hash<SR, 128, 9>(P, A, B, rows, nr, crp, ccol, cval);
-        case 10: return launch_num_hash<SR, 256, 10>(P, A, B, rows, nr, crp, ccol, cval);
-        case 11: return launch_num_hash<SR, 256, 11>(P, A, B, rows, nr, crp, ccol, cval);
-        case 12: return launch_num_hash<SR, 256, 12>(P, A, B, rows, nr, crp, ccol, cval);
+        case 7: return launch_num_hash<SR, 64, 7>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 8: return launch_num_hash<SR, 64, 8>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 9: return launch_num_hash<SR, 128, 9>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 10: return launch_num_hash<SR, 256, 10>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 11: return launch_num_hash<SR, 256, 11>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 12: return launch_num_hash<SR, 256, 12>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 13: return launch_num_hash<SR, 512, 13>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
     }
     return fail(SPG_ERR_ARG, "bad numeric hash bin");
 }
@@ -715,7 +737,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             }));
         } else if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "num_small", [&] {
-                k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval);
+                k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
             }));
         } else if (bb >= BIN_RANK0) {
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
@@ -728,8 +750,36 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                         cval);
                 });
             }));
-        } else if (bb == BIN_DENSE || bb == BIN_DENSE_PAR) {
-            const bool par = bb == BIN_DENSE_PAR;
+        } else if (bb == BIN_DENSE_PAR) {
+            const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
+            // an item holds at least one whole chunk (<= W outputs); group as
+            // many chunks as the LDS allows, up to RANKC_GROUP
+            const int32_t RC = std::max(RANKC_CAP, W);
+            int32_t G = std::min<int32_t>(chunks, MAX_CHUNKS);
+            while (G > 1 && (int64_t)G * (W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) --G;
+            SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(nr * chunks, 1), "rank items"));
+            SPG_TRY(P->small_i32.ensure(64 * 4, "counters"));
+            int32_t* nitems = P->small_i32.as<int32_t>() + 48;
+            SPG_TRY(fill_i32(P, nitems, 1, 0));
+            RankItem* items = P->rank_items.as<RankItem>();
+            const int32_t* hi = P->heavy_idx.as<int32_t>();
+            SPG_TRY(launch(P, "rank_items", [&] {
+                k_rank_items<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, (int32_t)nr, hi, P->chunk_save.as<int32_t>(),
+                                                                 chunks, RC, G, items, nitems);
+            }));
+            const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
+            const size_t lds = (size_t)G * (W / 32) * 8 + (size_t)RC * sizeof(typename Sr<SR>::acc_t);
+            const int32_t* split = chunks > 1 ? P->split.as<int32_t>() : nullptr;
+            const unsigned grid = (unsigned)std::min<int64_t>(nr * chunks, 256 * 8);
+            SPG_TRY(with_gm(P, [&](auto gm) {
+                return launch(P, "num_rankc", [&] {
+                    k_num_rankc<SR, 512, decltype(gm)::value><<<grid, 512, lds, cs(P)>>>(
+                        a, b, W, rows, ab, ae, P->bm_save.as<uint32_t>(), hi, nwords, split, chunks, items, nitems, RC, G,
+                        crp, ccol, cval);
+                });
+            }));
+        } else if (bb == BIN_DENSE) {
+            const bool par = false;
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             P->dense_chunks = chunks;
             const int32_t* split = nullptr;
@@ -1014,4 +1064,332 @@ extern "C" spg_status spg_profile_reset(spg_plan P) {
     P->prof_pending.clear();
     P->prof_acc.clear();
     return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// predictor: inference, gradient, Adam, training rows
+// ---------------------------------------------------------------------------
+extern "C" spg_status spg_mlp_forward(spg_plan P, const float* params, const float* x, int64_t n, float* y) {
+    if (!P || !params || (n > 0 && (!x || !y))) return fail(SPG_ERR_ARG, "NULL argument");
+    if (n <= 0) return SPG_OK;
+    P->cur = nullptr;
+    return launch(P, "mlp_forward", [&] { k_mlp_forward<<<grid_for(n, 256), 256, 0, cs(P)>>>(params, x, n, y); });
+}
+
+extern "C" spg_status spg_mlp_grad(spg_plan P, const float* params, const float* x, const float* t, int64_t n,
+                                   float alpha, float* grad, float* loss) {
+    if (!P || !params || !grad || (n > 0 && (!x || !t))) return fail(SPG_ERR_ARG, "NULL argument");
+    if (n <= 0) return SPG_OK;
+    P->cur = nullptr;
+    return launch(P, "mlp_grad", [&] {
+        k_mlp_grad<<<grid_for(n, MLP_BS), MLP_BS, 0, cs(P)>>>(params, x, t, n, alpha, grad, loss);
+    });
+}
+
+extern "C" spg_status spg_mlp_adam(spg_plan P, float* params, float* grad, float* m, float* v, int64_t step,
+                                   float lr, float beta1, float beta2, float eps) {
+    if (!P || !params || !grad || !m || !v || step < 1) return fail(SPG_ERR_ARG, "bad argument");
+    P->cur = nullptr;
+    return launch(P, "mlp_adam", [&] {
+        k_mlp_adam<<<grid_for(MLP_NPARAMS, 256), 256, 0, cs(P)>>>(params, grad, m, v, step, lr, beta1, beta2, eps);
+    });
+}
+
+extern "C" spg_status spg_row_training_data(spg_plan P, const int64_t* c_row_ptr, int64_t min_flops, float* x,
+                                            float* t, int64_t* nsel) {
+    if (!P || !c_row_ptr || !x || !t || !nsel) return fail(SPG_ERR_ARG, "NULL argument");
+    if (!P->have_symbolic) return fail(SPG_ERR_STATE, "needs a finished spgemm_symbolic on this plan");
+    P->cur = nullptr;
+    const int64_t m = P->sig.m;
+    SPG_TRY(P->mlp_tmp.ensure(64, "counter"));
+    unsigned long long* cnt = P->mlp_tmp.as<unsigned long long>();
+    SPG_TRY(fill_i64(P, (int64_t*)cnt, 1, 0));
+    if (m > 0) {
+        SPG_TRY(launch(P, "train_rows", [&] {
+            k_train_rows<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(),
+                                                              P->flops.as<int64_t>(), P->maxb.as<int32_t>(),
+                                                              P->opts.small_max_flops, min_flops, c_row_ptr, x, t,
+                                                              cnt);
+        }));
+    }
+    HIP_TRY(hipMemcpyAsync(P->h_stats, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    *nsel = P->h_stats[0];
+    return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-pass product with predicted sizes
+// ---------------------------------------------------------------------------
+static int fused_max_log2(spg_plan P, int64_t n) {
+    const int64_t nwords = (n + 31) / 32;
+    if (nwords > 8 * 512) return 0;  // the fused kernel keeps <= 8 bitmap words per thread
+    for (int lg = 14; lg >= RANK_MIN_LOG2; --lg)
+        if (nwords * 8 + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) return lg;
+    return 0;
+}
+
+template <int SR>
+static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
+    const int32_t* lists = P->lists.as<int32_t>();
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    const int64_t* slot = P->slot.as<int64_t>();
+    int64_t* cnt = P->lcnt.as<int64_t>() + 1;
+    int32_t* pcol = P->pcol.as<int32_t>();
+    void* pval = P->pval.p;
+    int64_t bin_off[NBINS + 1];
+    bin_off[0] = 0;
+    for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->l_counts[x];
+    SPG_TRY(fork_streams(P));
+    const std::vector<int> order = bins_by_work(P->l_counts, P->l_counts + NBINS);
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const int bb = order[oi];
+        const int64_t nr = P->l_counts[bb];
+        const int32_t* rows = lists + bin_off[bb];
+        if (nr == 0 || bb == BIN_EMPTY || bb == BIN_DENSE) continue;
+        use_stream(P, (int)oi);
+        if (bb == BIN_TINY) {
+            SPG_TRY(launch(P, "num_tiny", [&] {
+                k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, slot, pcol, pval);
+            }));
+        } else if (bb == BIN_SMALL) {
+            SPG_TRY(launch(P, "num_small", [&] {
+                k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, slot, pcol, pval,
+                                                                     cnt);
+            }));
+        } else if (bb >= BIN_RANK0) {
+            const int64_t acc_cap = 4096ll << (bb - BIN_RANK0);
+            const size_t lds = (size_t)nwords * 8 + (size_t)acc_cap * sizeof(typename Sr<SR>::acc_t);
+            SPG_TRY(with_gm(P, [&](auto gm) {
+                return launch(P, "learned_fused" + std::to_string(acc_cap), [&] {
+                    k_learned_fused<SR, 512, decltype(gm)::value><<<(unsigned)nr, 512, lds, cs(P)>>>(
+                        a, b, rows, ab, ae, nwords, acc_cap, slot, cnt, pcol, pval);
+                });
+            }, true));
+        } else {
+            SPG_TRY(num_hash_dispatch<SR>(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, slot, pcol, pval, cnt));
+        }
+    }
+    return join_streams(P);
+}
+
+template <int SR>
+static spg_status gather_sub_rows(spg_plan P, Csr a) {
+    const int32_t nl = (int32_t)P->l_nfb;
+    SPG_TRY(P->sub_rp.ensure(8 * (size_t)(nl + 1), "recomputed rows"));
+    int64_t* srp = P->sub_rp.as<int64_t>();
+    SPG_TRY(launch(P, "gather_len", [&] {
+        k_gather_len<<<grid_for(nl, 256), 256, 0, cs(P)>>>(a.rp, P->fb_list.as<int32_t>(), nl, srp + 1);
+    }));
+    SPG_TRY(scan_counts(P, srp, nl));
+    HIP_TRY(hipMemcpyAsync(P->h_stats, srp + nl, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    const int64_t annz = P->h_stats[0];
+    P->l_sub_annz = annz;
+    const size_t w = SR == SR_BOOL ? 1 : 8;
+    SPG_TRY(P->sub_col.ensure(4 * (size_t)std::max<int64_t>(annz, 1), "recomputed rows"));
+    SPG_TRY(P->sub_val.ensure(w * (size_t)std::max<int64_t>(annz, 1), "recomputed rows"));
+    SPG_TRY(launch(P, "gather_rows", [&] {
+        k_gather_rows<SR><<<grid_for(nl, 4), 256, 0, cs(P)>>>(a, P->fb_list.as<int32_t>(), nl, srp,
+                                                               P->sub_col.as<int32_t>(), P->sub_val.p);
+    }));
+    return SPG_OK;
+}
+
+static spg_csr sub_matrix(spg_plan P, const spg_csr* A) {
+    spg_csr s;
+    s.nrows = P->l_nfb;
+    s.ncols = A->ncols;
+    s.nnz = P->l_sub_annz;
+    s.row_ptr = P->sub_rp.as<int64_t>();
+    s.col = P->sub_col.as<int32_t>();
+    s.val = P->sub_val.p;
+    return s;
+}
+
+extern "C" spg_status spgemm_learned_run(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B,
+                                         int64_t k_lo, int64_t k_hi, const float* mlp_params, float margin,
+                                         int64_t* c_nnz, spg_learned_stats* st) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->cur = nullptr;
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    SPG_TRY(check_csr(A, "A", sr, true));
+    SPG_TRY(check_csr(B, "B", sr, true));
+    if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
+    if (A->nrows > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split A by rows");
+    if (k_lo < 0 || k_hi < k_lo || k_hi > A->ncols) return fail(SPG_ERR_ARG, "window must satisfy 0 <= k_lo <= k_hi <= A.ncols");
+    if (!c_nnz) return fail(SPG_ERR_ARG, "c_nnz is NULL");
+    if (!(margin >= 0.f) || margin > 100.f) return fail(SPG_ERR_ARG, "margin must be in [0, 100]");
+    P->have_learned = false;
+    P->have_symbolic = false;
+    P->num_counts_valid = false;
+    const int64_t m = A->nrows, n = B->ncols;
+    if (P->opts.validate) {
+        SPG_TRY(validate_csr(P, A, "A"));
+        SPG_TRY(validate_csr(P, B, "B"));
+    }
+    SPG_TRY(ensure_rows(P, m));
+    const size_t mm = (size_t)std::max<int64_t>(m, 1);
+    SPG_TRY(P->lcap.ensure(8 * mm, "capacities"));
+    SPG_TRY(P->lcnt.ensure(8 * (mm + 1), "counts"));
+    SPG_TRY(P->slot.ensure(8 * (mm + 1), "slots"));
+    SPG_TRY(P->fb_list.ensure(4 * mm, "recomputed rows"));
+    SPG_TRY(P->fb_redo.ensure(mm, "recomputed rows"));
+    Csr a = view(A), b = view(B);
+    BinParams bp = bin_params(P, n);
+    int64_t* stats = P->stats.as<int64_t>();
+    int32_t* ctr = P->small_i32.as<int32_t>();
+    int64_t* cnt = P->lcnt.as<int64_t>() + 1;
+    const int full = (k_lo == 0 && k_hi == A->ncols) ? 1 : 0;
+    SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
+    SPG_TRY(fill_i32(P, ctr, 2 + NBINS, 0));
+    RowInfoOut o{P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), P->flops.as<int64_t>(), P->maxb.as<int32_t>(),
+                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr};
+    LearnedParams lp;
+    lp.margin = margin;
+    lp.use_mlp = mlp_params ? 1 : 0;
+    lp.fused_max_log2 = fused_max_log2(P, n);
+    lp.hash_max_nnz = P->opts.hash_max_nnz;
+    if (m > 0) {
+        SPG_TRY(launch(P, "rowinfo", [&] {
+            k_rowinfo<<<grid_for(m, 16), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
+        }));
+        SPG_TRY(launch(P, "rowinfo_long", [&] {
+            k_rowinfo_long<<<256, 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
+        }));
+        SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
+        SPG_TRY(launch(P, "learned_classify", [&] {
+            k_learned_classify<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, n, mlp_params, lp, bp, P->a_beg.as<int64_t>(),
+                                                                    P->a_end.as<int64_t>(), P->flops.as<int64_t>(),
+                                                                    P->maxb.as<int32_t>(), P->bin.as<uint8_t>(),
+                                                                    P->lcap.as<int64_t>(), cnt, stats);
+        }));
+        SPG_TRY(launch(P, "bin_scatter", [&] {
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), stats, ctr + 2,
+                                                               P->lists.as<int32_t>());
+        }));
+        HIP_TRY(hipMemcpyAsync(P->slot.as<int64_t>() + 1, P->lcap.p, 8 * (size_t)m, hipMemcpyDeviceToDevice, cs(P)));
+    }
+    SPG_TRY(scan_counts(P, P->slot.as<int64_t>(), m));
+    HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 2 * NBINS, hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipMemcpyAsync(P->h_stats + 2 * NBINS, P->slot.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    std::memcpy(P->l_counts, P->h_stats, sizeof(int64_t) * 2 * NBINS);
+    P->l_slots = P->h_stats[2 * NBINS];
+    P->l_nexact = P->l_counts[BIN_DENSE];
+    const size_t w = sr == SPG_SR_OR_AND_BOOL ? 1 : 8;
+    SPG_TRY(P->pcol.ensure(4 * (size_t)std::max<int64_t>(P->l_slots, 1), "padded output"));
+    SPG_TRY(P->pval.ensure(w * (size_t)std::max<int64_t>(P->l_slots, 1), "padded output"));
+    const int32_t nwords = (int32_t)((n + 31) / 32);
+    spg_status stt = SPG_OK;
+    switch (sr) {
+        case SPG_SR_PLUS_TIMES_F64: stt = learned_launch<SR_F64>(P, a, b, nwords); break;
+        case SPG_SR_PLUS_TIMES_I64: stt = learned_launch<SR_I64>(P, a, b, nwords); break;
+        case SPG_SR_OR_AND_BOOL: stt = learned_launch<SR_BOOL>(P, a, b, nwords); break;
+    }
+    SPG_TRY(stt);
+    // rows the exact method must compute
+    SPG_TRY(fill_i32(P, ctr, 1, 0));
+    if (m > 0) {
+        SPG_TRY(launch(P, "fallback_rows", [&] {
+            k_fallback_rows<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), P->lcap.as<int64_t>(), cnt,
+                                                                 P->fb_list.as<int32_t>(), ctr, P->fb_redo.as<uint8_t>());
+        }));
+    }
+    int32_t hfb = 0;
+    HIP_TRY(hipMemcpyAsync(&hfb, ctr, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    P->l_nfb = hfb;
+    P->l_sub_nnz = 0;
+    if (hfb > 0) {
+        switch (sr) {
+            case SPG_SR_PLUS_TIMES_F64: stt = gather_sub_rows<SR_F64>(P, a); break;
+            case SPG_SR_PLUS_TIMES_I64: stt = gather_sub_rows<SR_I64>(P, a); break;
+            case SPG_SR_OR_AND_BOOL: stt = gather_sub_rows<SR_BOOL>(P, a); break;
+        }
+        SPG_TRY(stt);
+        if (!P->sub) SPG_TRY(spg_plan_create(&P->sub, (void*)P->stream, &P->opts));
+        P->sub->stream = P->stream;
+        SPG_TRY(P->sub_crp.ensure(8 * (size_t)(hfb + 1), "recomputed rows"));
+        spg_csr S = sub_matrix(P, A);
+        int64_t snnz = 0;
+        SPG_TRY(spgemm_symbolic(P->sub, sr, &S, B, k_lo, k_hi, P->sub_crp.as<int64_t>(), &snnz));
+        P->l_sub_nnz = snnz;
+        SPG_TRY(launch(P, "scatter_counts", [&] {
+            k_scatter_counts<<<grid_for(hfb, 256), 256, 0, cs(P)>>>(P->fb_list.as<int32_t>(), hfb,
+                                                                    P->sub_crp.as<int64_t>(), cnt);
+        }));
+    }
+    SPG_TRY(scan_counts(P, P->lcnt.as<int64_t>(), m));
+    HIP_TRY(hipMemcpyAsync(P->h_stats, P->lcnt.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    P->l_nnz = P->h_stats[0];
+    *c_nnz = P->l_nnz;
+    Signature sg;
+    sg.a_rp = A->row_ptr; sg.a_col = A->col; sg.b_rp = B->row_ptr; sg.b_col = B->col;
+    sg.m = m; sg.n = n; sg.k = A->ncols; sg.annz = A->nnz; sg.bnnz = B->nnz; sg.k_lo = k_lo; sg.k_hi = k_hi;
+    P->lsig = sg;
+    P->l_sr = sr;
+    P->have_learned = true;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        int64_t pred = 0;
+        for (int x = BIN_HASH0; x < NBINS; ++x)
+            if (x != BIN_DENSE) pred += P->l_counts[x];
+        st->rows_predicted = pred;
+        st->rows_exact = P->l_nexact;
+        st->rows_overflow = P->l_nfb - P->l_nexact;
+        st->slots = P->l_slots;
+        st->nnz_c = P->l_nnz;
+        st->nnz_single = P->l_nnz - P->l_sub_nnz;
+        for (int x = 0; x < NBINS; ++x) st->bin_rows[x] = P->l_counts[x];
+    }
+    return SPG_OK;
+}
+
+template <int SR>
+static spg_status learned_fetch_sr(spg_plan P, const spg_csr* A, const spg_csr* B, int64_t* c_row_ptr,
+                                   int32_t* c_col, void* c_val) {
+    const int64_t m = P->lsig.m;
+    if (m > 0) {
+        SPG_TRY(launch(P, "copy_rows", [&] {
+            k_copy_rows<SR><<<grid_for(m, 4), 256, 0, cs(P)>>>(m, nullptr, P->fb_redo.as<uint8_t>(), P->slot.as<int64_t>(),
+                                                                c_row_ptr, P->pcol.as<int32_t>(), P->pval.p, c_col, c_val);
+        }));
+    }
+    if (P->l_nfb > 0) {
+        const size_t w = SR == SR_BOOL ? 1 : 8;
+        SPG_TRY(P->sub_ccol.ensure(4 * (size_t)std::max<int64_t>(P->l_sub_nnz, 1), "recomputed output"));
+        SPG_TRY(P->sub_cval.ensure(w * (size_t)std::max<int64_t>(P->l_sub_nnz, 1), "recomputed output"));
+        spg_csr S = sub_matrix(P, A);
+        SPG_TRY(spgemm_numeric(P->sub, P->l_sr, &S, B, P->lsig.k_lo, P->lsig.k_hi, P->sub_crp.as<int64_t>(),
+                               P->sub_ccol.as<int32_t>(), c_val ? P->sub_cval.p : nullptr));
+        P->cur = nullptr;
+        SPG_TRY(launch(P, "copy_rows", [&] {
+            k_copy_rows<SR><<<grid_for(P->l_nfb, 4), 256, 0, cs(P)>>>(P->l_nfb, P->fb_list.as<int32_t>(), nullptr,
+                                                                       P->sub_crp.as<int64_t>(), c_row_ptr,
+                                                                       P->sub_ccol.as<int32_t>(), P->sub_cval.p, c_col,
+                                                                       c_val);
+        }));
+    }
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_learned_fetch(spg_plan P, const spg_csr* A, const spg_csr* B, int64_t* c_row_ptr,
+                                           int32_t* c_col, void* c_val) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->cur = nullptr;
+    if (!A || !B || !c_row_ptr) return fail(SPG_ERR_ARG, "NULL argument");
+    if (!P->have_learned || P->lsig.a_rp != A->row_ptr || P->lsig.b_rp != B->row_ptr || P->lsig.m != A->nrows)
+        return fail(SPG_ERR_STATE, "spgemm_learned_fetch needs the matching spgemm_learned_run first");
+    if (P->l_nnz > 0 && !c_col) return fail(SPG_ERR_ARG, "c_col is NULL");
+    HIP_TRY(hipMemcpyAsync(c_row_ptr, P->lcnt.p, 8 * (size_t)(P->lsig.m + 1), hipMemcpyDeviceToDevice, P->stream));
+    switch (P->l_sr) {
+        case SPG_SR_PLUS_TIMES_F64: return learned_fetch_sr<SR_F64>(P, A, B, c_row_ptr, c_col, c_val);
+        case SPG_SR_PLUS_TIMES_I64: return learned_fetch_sr<SR_I64>(P, A, B, c_row_ptr, c_col, c_val);
+        case SPG_SR_OR_AND_BOOL: return learned_fetch_sr<SR_BOOL>(P, A, B, c_row_ptr, c_col, c_val);
+    }
+    return fail(SPG_ERR_ARG, "unknown semiring");
 }

@@ -103,6 +103,9 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* ro
 // The finished bitmap is the row's stored set; it is written to bm_save
 // (slot = position in the bin list, recorded in heavy_idx) so the numeric
 // pass can place values by rank without gathering the columns again.
+// When n exceeds 32*nwords columns the row is counted in column blocks of
+// that width, each block gathering all of the row's products and keeping
+// those inside it; bitmaps are saved only in the single-block case.
 template <int NT, int GM>
 __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* rows,
                                                    const int64_t* a_beg, const int64_t* a_end,
@@ -114,6 +117,32 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
     __shared__ int32_t red[NT / SPG_WAVE + 1];
     __shared__ int32_t s_chunk[MAX_CHUNKS];
     const int64_t i = rows[blockIdx.x];
+    const int64_t block_cols = (int64_t)nwords * 32;
+    if (B.ncols > block_cols) {
+        int64_t total = 0;
+        for (int64_t cb = 0; cb < B.ncols; cb += block_cols) {
+            for (int t = threadIdx.x; t < nwords; t += NT) bm[t] = 0u;
+            __syncthreads();
+            for_each_product_gm<NT, GM>(
+                a_beg[i], a_end[i], L,
+                [&](int64_t p, int64_t& bs, int32_t& len) {
+                    int64_t k = A.col[p];
+                    bs = B.rp[k];
+                    len = (int32_t)(B.rp[k + 1] - bs);
+                },
+                [&](int, int64_t) {},
+                [&](int64_t q) { return (int64_t)B.col[q]; },
+                [&](int, int64_t j) {
+                    const int64_t jj = j - cb;
+                    if (jj >= 0 && jj < block_cols) atomicOr(&bm[jj >> 5], 1u << (jj & 31));
+                });
+            int32_t mine = 0;
+            for (int t = threadIdx.x; t < nwords; t += NT) mine += __popc(bm[t]);
+            total += block_reduce_add<NT, int32_t>(mine, red);
+        }
+        if (threadIdx.x == 0) cnt[i] = total;
+        return;
+    }
     for (int t = threadIdx.x; t < nwords; t += NT) bm[t] = 0u;
     for (int t = threadIdx.x; t < MAX_CHUNKS; t += NT) s_chunk[t] = 0;
     __syncthreads();

@@ -48,6 +48,6 @@ def test_host_only_entry_points():
     assert L.spg_status_string(2) == b"SPG_ERR_SHAPE"
     o = spg.Opts()
     L.spg_default_opts(ctypes.byref(o))
-    assert o.small_max_flops == 64 and o.hash_max_nnz == 2048 and o.streams == 4
+    assert o.small_max_flops == 64 and o.hash_max_nnz == 4096 and o.streams == 4
     assert ctypes.sizeof(spg.Opts) == 16 * 4
     assert ctypes.sizeof(spg._Csr) == 6 * 8
