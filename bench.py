@@ -74,7 +74,9 @@ def kernel_bytes(name: str, st: dict, sr: str) -> float:
     bins = {"tiny": [1], "small": [2], "dense": [12], "bitmap": [12], "dense_par": [11]}
     kind, _, tail = name.partition("_")
     b = None
-    if tail.startswith("hash"):
+    if tail == "rankc":
+        idx = [11]
+    elif tail.startswith("hash"):
         T = int(tail[4:])
         b = 3 + (T.bit_length() - 1 - 7)
         idx = [b]
@@ -164,6 +166,99 @@ def learned_modes(A2, dA2, args):
         import torch
         torch.cuda.empty_cache()
     return res
+
+
+def batched_modes(args):
+    """64 AMG Galerkin products (R^T A) R, A = 7-point Poisson on N^3 grids
+    with N uniform in [16, 64], R = 2x2x2 aggregation: one batched call
+    replayed as a HIP graph, the same batched call without the graph, and
+    the 128 products one by one with the plain two-phase entry points."""
+    import torch
+
+    import paper_1510_00844_amd as spg
+    import synth
+    sizes, inst = synth.galerkin_batch()
+    dev = []
+    for RT, A, R in inst:
+        dev.append(tuple(spg.DeviceCSR.from_arrays(M.nrows, M.ncols, M.row_ptr, M.col, M.val) for M in (RT, A, R)))
+    rts, As, Rs = [d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev]
+    flops = sum(A.nnz for _, A, _ in inst)  # flops(R^T, A) = nnz(A): one entry per column of R^T
+    plan = spg.Plan()
+    res = spg.spgemm_galerkin_batched(plan, "f64", rts, As, Rs, use_graph=True)
+    flops += sum(int(n) for n in _t_nnz(plan, rts, As))  # flops(T, R) = nnz(T): one entry per row of R
+    reps = 20
+    t_graph, _ = _time(lambda: spg.spgemm_galerkin_batched(plan, "f64", rts, As, Rs, use_graph=True), reps)
+    plan_e = spg.Plan()
+    spg.spgemm_galerkin_batched(plan_e, "f64", rts, As, Rs, use_graph=False)
+    t_eager, _ = _time(lambda: spg.spgemm_galerkin_batched(plan_e, "f64", rts, As, Rs, use_graph=False), reps)
+    plan_s = spg.Plan()
+
+    def seq():
+        for rt, a, r in dev:
+            T = spg.spgemm(plan_s, "f64", rt, a)
+            spg.spgemm(plan_s, "f64", T, r)
+
+    t_seq, _ = _time(seq, 3)
+    nnz_c = sum(res.nnz)
+    g = lambda t: round(2.0 * flops / (t * 1e-3) / 1e9, 3)
+    out = {"workload": "64 x (R^T A) R, A 7-point Poisson N^3 (N uniform 16..64, seed 5), R 2x2x2 aggregation, FP64",
+           "grid_sizes": [int(x) for x in sizes], "flops": flops, "nnz_c": nnz_c,
+           "graph_replay": {"ms": round(t_graph, 4), "gflops": g(t_graph)},
+           "batched_no_graph": {"ms": round(t_eager, 4), "gflops": g(t_eager)},
+           "sequential_128_products": {"ms": round(t_seq, 4), "gflops": g(t_seq)},
+           "speedup_graph_vs_sequential": round(t_seq / t_graph, 3)}
+    for p in (plan, plan_e, plan_s):
+        p.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _t_nnz(plan, rts, As):
+    """nnz(R_b^T A_b) per instance, from the two-phase symbolic pass."""
+    import paper_1510_00844_amd as spg
+    out = []
+    for rt, a in zip(rts, As):
+        _, nnz = spg.spgemm_symbolic(plan, "f64", rt, a)
+        out.append(nnz)
+    return out
+
+
+def layered_modes(args):
+    """Split-3D layer shape: ER scale 18, edge factor 16; the inner dimension
+    in c contiguous layers, C_l = A(:,K_l) B(K_l,:), then the merge."""
+    import torch
+
+    import paper_1510_00844_amd as spg
+    import synth
+    A = synth.rmat(18, 16, synth.ER, seed=3)
+    B = synth.rmat(18, 16, synth.ER, seed=4)
+    dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
+    dB = spg.DeviceCSR.from_arrays(B.nrows, B.ncols, B.row_ptr, B.col, B.val)
+    plan = spg.Plan()
+    t_full, C = _time(lambda: spg.spgemm(plan, "f64", dA, dB), 3)
+    flops = plan.stats()["flops"]
+    out = {"workload": "ER (.25,.25,.25,.25) scale 18 edge factor 16, A*B FP64", "flops": flops,
+           "nnz_c": C.nnz, "unsplit": {"ms": round(t_full, 4), "gflops": round(2.0 * flops / t_full / 1e6, 3)}}
+    for c in (4, 16):
+        bounds = synth.layer_bounds(A.ncols, c)
+        layers = []
+
+        def products():
+            layers.clear()
+            for lo, hi in bounds:
+                layers.append(spg.spgemm(plan, "f64", dA, dB, lo, hi))
+            return layers
+
+        t_prod, _ = _time(products, 3)
+        t_merge, M = _time(lambda: spg.spgemm_merge_layers(plan, "f64", layers), 3)
+        assert M.nnz == C.nnz
+        out["c%d" % c] = {"layers_ms": round(t_prod, 4), "merge_ms": round(t_merge, 4),
+                          "gflops_layers": round(2.0 * flops / t_prod / 1e6, 3),
+                          "layer_nnz": sum(L.nnz for L in layers)}
+        del layers
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -272,6 +367,8 @@ def main():
                                    "hbm_model_gbs": round(model_bytes(A.nrows, A.nnz, flops, n2, xsr) / (xms * 1e-3) / 1e9, 2)}
             p2.close()
         extras.update(learned_modes(A, dA, args))
+        extras["c4_batched"] = batched_modes(args)
+        extras["c3_layers"] = layered_modes(args)
         out["modes"] = extras
     if not args.no_cpu_baseline:
         import oracle

@@ -225,6 +225,31 @@ spg_status spgemm_learned_run(spg_plan plan, spg_semiring sr, const spg_csr* A, 
 spg_status spgemm_learned_fetch(spg_plan plan, const spg_csr* A, const spg_csr* B, int64_t* c_row_ptr,
                                 int32_t* c_col, void* c_val);
 
+/* ------------------------------------------------------------------------
+ * Batched Galerkin products (the restriction experiments of Section 5.3,
+ * computed as (R^T A) R): for b < nb, out[b] = (RT[b] A[b]) R[b], with RT[b]
+ * M_b x N_b, A[b] N_b x N_b', R[b] N_b' x M_b.  RT, A, R and out are HOST
+ * arrays of nb descriptors; the matrices are device CSR.  The instances are
+ * multiplied as one block-diagonal product, so every launch covers all
+ * instances.  The first call with a given set of descriptors runs eagerly
+ * (and synchronizes); with use_graph it then captures the whole device
+ * sequence into one HIP graph, which later calls with the same descriptors
+ * (same pointers and sizes; values may change) replay without any host
+ * synchronization.  out[b] points into plan-owned memory (column indices
+ * local to the instance), valid until the next call with other descriptors
+ * or spg_plan_destroy.  Calls that overlap on one plan race.
+ * ------------------------------------------------------------------------ */
+spg_status spgemm_galerkin_batched(spg_plan plan, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                                   const spg_csr* A, const spg_csr* R, spg_csr* out, int32_t use_graph);
+
+/* Copies the last batched result into caller-owned device buffers, on the
+ * plan's stream: row_ptr gets, for each instance in order, its M_b + 1 row
+ * pointers starting at 0 (sum of M_b + nb entries); col and val get the
+ * instances' entries back to back (sum of out[b].nnz entries; column indices
+ * local to the instance).  val may be NULL.  SPG_ERR_STATE without a
+ * batched call on the plan. */
+spg_status spgemm_galerkin_copy(spg_plan plan, int64_t* row_ptr, int32_t* col, void* val);
+
 const char* spg_status_string(spg_status s);
 const char* spg_last_error(void);
 

@@ -103,6 +103,8 @@ def lib():
             "spgemm_learned_run": ([P, ctypes.c_int, CP, CP, I64, I64, P, ctypes.c_float, ctypes.POINTER(I64),
                                     ctypes.POINTER(LearnedStats)], ctypes.c_int),
             "spgemm_learned_fetch": ([P, CP, CP, P, P, P], ctypes.c_int),
+            "spgemm_galerkin_batched": ([P, ctypes.c_int, I32, CP, CP, CP, CP, I32], ctypes.c_int),
+            "spgemm_galerkin_copy": ([P, P, P, P], ctypes.c_int),
             "spg_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "spg_last_error": ([], ctypes.c_char_p),
         }
@@ -326,3 +328,50 @@ def spgemm_learned_fetch(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, nnz: i
 def spgemm_learned(plan: Plan, sr: str, A: DeviceCSR, B: DeviceCSR, params, margin=0.15, k_lo=None, k_hi=None):
     nnz, st = spgemm_learned_run(plan, sr, A, B, params, margin, k_lo, k_hi)
     return spgemm_learned_fetch(plan, sr, A, B, nnz), st
+
+
+class GalerkinBatch:
+    """Result descriptors of one spgemm_galerkin_batched call (device memory
+    owned by the plan)."""
+
+    def __init__(self, out, sr):
+        self.out = out
+        self.sr = sr
+
+    @property
+    def nnz(self):
+        return [int(o.nnz) for o in self.out]
+
+    def fetch(self, plan: "Plan", values=True) -> list:
+        """Copy the instances into torch tensors (one DeviceCSR each)."""
+        nb = len(self.out)
+        rows = [int(o.nrows) for o in self.out]
+        nnz = self.nnz
+        tot = sum(nnz)
+        rp = torch.empty(sum(rows) + nb, dtype=torch.int64, device=plan.device)
+        col = torch.empty(max(tot, 1), dtype=torch.int32, device=plan.device)
+        val = torch.empty(max(tot, 1), dtype=TORCH_DTYPE[self.sr], device=plan.device) if values else None
+        _check(lib().spgemm_galerkin_copy(plan.handle, _vp(rp), _vp(col), _vp(val)))
+        res, r0, z0 = [], 0, 0
+        for b in range(nb):
+            res.append(DeviceCSR(rows[b], int(self.out[b].ncols), rp[r0:r0 + rows[b] + 1], col[z0:z0 + nnz[b]],
+                                 None if val is None else val[z0:z0 + nnz[b]]))
+            r0 += rows[b] + 1
+            z0 += nnz[b]
+        return res
+
+
+def spgemm_galerkin_batched(plan: Plan, sr: str, RT: Sequence[DeviceCSR], A: Sequence[DeviceCSR],
+                            R: Sequence[DeviceCSR], use_graph=True) -> GalerkinBatch:
+    """C_b = (RT_b A_b) R_b for all b in one block-diagonal product; with
+    use_graph, repeated calls on the same matrices replay one HIP graph."""
+    nb = len(A)
+    if not (len(RT) == len(R) == nb):
+        raise ValueError("RT, A and R need the same number of instances")
+    keep = (RT, A, R)  # noqa: F841  (descriptors reference these tensors)
+    rt = (_Csr * nb)(*[m._c(sr) for m in RT])
+    a = (_Csr * nb)(*[m._c(sr) for m in A])
+    r = (_Csr * nb)(*[m._c(sr) for m in R])
+    out = (_Csr * nb)()
+    _check(lib().spgemm_galerkin_batched(plan.handle, SEMIRINGS[sr], nb, rt, a, r, out, int(bool(use_graph))))
+    return GalerkinBatch(out, sr)

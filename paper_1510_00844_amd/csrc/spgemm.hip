@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/spgemm.h"
+#include "batched.hpp"
 #include "learned.hpp"
 #include "merge.hpp"
 #include "numeric.hpp"
@@ -106,6 +107,10 @@ struct spg_plan_s {
     int h_layers_cap = 0;
 
     Signature sig;
+    // frozen: reuse the bin counts of the previous call with the same
+    // structure instead of reading them back (no host synchronization, so the
+    // calls can be captured into a HIP graph)
+    bool frozen = false;
     bool have_symbolic = false;
     bool num_counts_valid = false;
     int64_t sym_counts[3 * NBINS];
@@ -353,9 +358,12 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     return SPG_OK;
 }
 
+void spg_release_galerkin(spg_plan P);
+
 extern "C" spg_status spg_plan_destroy(spg_plan P) {
     if (!P) return SPG_OK;
     hipStreamSynchronize(P->stream);
+    spg_release_galerkin(P);
     for (DevBuf* b : {&P->a_beg, &P->a_end, &P->flops, &P->maxb, &P->bin, &P->lists, &P->long_rows,
                       &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
                       &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save, &P->rank_items,
@@ -582,9 +590,11 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                                                                    P->lists.as<int32_t>());
         }));
     }
-    HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 3 * NBINS, hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
-    std::memcpy(P->sym_counts, P->h_stats, sizeof(int64_t) * 3 * NBINS);
+    if (!P->frozen) {
+        HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 3 * NBINS, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        std::memcpy(P->sym_counts, P->h_stats, sizeof(int64_t) * 3 * NBINS);
+    }
     int64_t tot = 0;
     for (int x = 0; x < NBINS; ++x) tot += P->sym_counts[NBINS + x];
     P->last_flops = tot;
@@ -660,6 +670,11 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     s.m = m; s.n = n; s.k = A->ncols; s.annz = A->nnz; s.bnnz = B->nnz; s.k_lo = k_lo; s.k_hi = k_hi;
     P->sig = s;
     P->have_symbolic = true;
+    if (P->frozen) {
+        P->num_counts_valid = true;  // counts of the previous call
+        if (c_nnz) *c_nnz = P->last_nnz;
+        return SPG_OK;
+    }
     if (c_nnz) {
         HIP_TRY(hipMemcpyAsync(P->h_stats, nstats, sizeof(int64_t) * 4 * NBINS, hipMemcpyDeviceToHost, P->stream));
         HIP_TRY(hipMemcpyAsync(P->h_stats + 4 * NBINS, c_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
@@ -1392,4 +1407,297 @@ extern "C" spg_status spgemm_learned_fetch(spg_plan P, const spg_csr* A, const s
         case SPG_SR_OR_AND_BOOL: return learned_fetch_sr<SR_BOOL>(P, A, B, c_row_ptr, c_col, c_val);
     }
     return fail(SPG_ERR_ARG, "unknown semiring");
+}
+
+// ---------------------------------------------------------------------------
+// batched Galerkin products C_b = (RT_b A_b) R_b
+// ---------------------------------------------------------------------------
+struct GalerkinState {
+    std::vector<spg_csr> sig_rt, sig_a, sig_r;
+    spg_semiring sr = SPG_SR_PLUS_TIMES_F64;
+    int32_t nb = 0;
+    DevBuf desc, rt_rp, rt_col, rt_val, a_rp, a_col, a_val, r_rp, r_col, r_val;
+    DevBuf t_rp, t_col, t_val, c_rp, c_col, c_val, out_rp;
+    spg_plan p1 = nullptr, p2 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // the sequence runs (and is captured) on this stream, ordered after and
+    // before the caller's stream by events; capture is not possible on the
+    // legacy default stream a caller may pass
+    hipStream_t gs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int64_t rows_rt = 0, cols_rt = 0, nnz_rt = 0, rows_a = 0, nnz_a = 0, rows_r = 0, cols_r = 0, nnz_r = 0;
+    int64_t nnz_t = 0, nnz_c = 0;
+    std::vector<BatchDesc> h_desc;  // [rt | a | r | c] tables
+    std::vector<int64_t> c_base;    // first entry of each instance in C
+    bool valid = false;
+};
+
+static GalerkinState* galerkin_state(spg_plan P);
+static spg_status galerkin_run(spg_plan P, GalerkinState* G, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                               const spg_csr* A, const spg_csr* R, int32_t use_graph);
+static void galerkin_free(GalerkinState* G);
+
+static bool same_csr(const spg_csr& x, const spg_csr& y) {
+    return x.nrows == y.nrows && x.ncols == y.ncols && x.nnz == y.nnz && x.row_ptr == y.row_ptr && x.col == y.col &&
+           x.val == y.val;
+}
+
+// The whole device sequence of one batched call.  eager: may allocate and
+// read sizes back; otherwise (graph capture) only launches, with the sizes
+// of the eager call.
+static spg_status galerkin_sequence(spg_plan P, GalerkinState* G, bool eager) {
+    const int32_t nb = G->nb;
+    const BatchDesc* d = G->desc.as<BatchDesc>();
+    const int32_t vw = G->sr == SPG_SR_OR_AND_BOOL ? 1 : 8;
+    P->cur = G->gs;
+    // the assembled operands are canonical when the instances are; only the
+    // eager call may synchronize
+    G->p1->opts.validate = G->p2->opts.validate = eager ? P->opts.validate : 0;
+    SPG_TRY(launch(P, "batch_assemble", [&] {
+        k_batch_assemble<<<grid_for(G->rows_rt + 1, 256), 256, 0, cs(P)>>>(d, nb, G->rows_rt, G->nnz_rt, vw,
+                                                                          G->rt_rp.as<int64_t>(), G->rt_col.as<int32_t>(),
+                                                                          G->rt_val.p);
+    }));
+    SPG_TRY(launch(P, "batch_assemble", [&] {
+        k_batch_assemble<<<grid_for(G->rows_a + 1, 256), 256, 0, cs(P)>>>(d + nb, nb, G->rows_a, G->nnz_a, vw,
+                                                                         G->a_rp.as<int64_t>(), G->a_col.as<int32_t>(),
+                                                                         G->a_val.p);
+    }));
+    SPG_TRY(launch(P, "batch_assemble", [&] {
+        k_batch_assemble<<<grid_for(G->rows_r + 1, 256), 256, 0, cs(P)>>>(d + 2 * nb, nb, G->rows_r, G->nnz_r, vw,
+                                                                         G->r_rp.as<int64_t>(), G->r_col.as<int32_t>(),
+                                                                         G->r_val.p);
+    }));
+    spg_csr RT{G->rows_rt, G->cols_rt, G->nnz_rt, G->rt_rp.as<int64_t>(), G->rt_col.as<int32_t>(), G->rt_val.p};
+    spg_csr A{G->rows_a, G->rows_r, G->nnz_a, G->a_rp.as<int64_t>(), G->a_col.as<int32_t>(), G->a_val.p};
+    spg_csr R{G->rows_r, G->cols_r, G->nnz_r, G->r_rp.as<int64_t>(), G->r_col.as<int32_t>(), G->r_val.p};
+    const size_t w = vw;
+    int64_t nt = G->nnz_t, nc = G->nnz_c;
+    if (eager) SPG_TRY(G->t_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched T"));
+    SPG_TRY(spgemm_symbolic(G->p1, G->sr, &RT, &A, 0, A.nrows, G->t_rp.as<int64_t>(), eager ? &nt : nullptr));
+    if (eager) {
+        G->nnz_t = nt;
+        SPG_TRY(G->t_col.ensure(4 * (size_t)std::max<int64_t>(nt, 1), "batched T"));
+        SPG_TRY(G->t_val.ensure(w * (size_t)std::max<int64_t>(nt, 1), "batched T"));
+    }
+    SPG_TRY(spgemm_numeric(G->p1, G->sr, &RT, &A, 0, A.nrows, G->t_rp.as<int64_t>(), G->t_col.as<int32_t>(), G->t_val.p));
+    spg_csr T{G->rows_rt, G->rows_r, G->nnz_t, G->t_rp.as<int64_t>(), G->t_col.as<int32_t>(), G->t_val.p};
+    if (eager) SPG_TRY(G->c_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched C"));
+    SPG_TRY(spgemm_symbolic(G->p2, G->sr, &T, &R, 0, R.nrows, G->c_rp.as<int64_t>(), eager ? &nc : nullptr));
+    if (eager) {
+        G->nnz_c = nc;
+        SPG_TRY(G->c_col.ensure(4 * (size_t)std::max<int64_t>(nc, 1), "batched C"));
+        SPG_TRY(G->c_val.ensure(w * (size_t)std::max<int64_t>(nc, 1), "batched C"));
+        SPG_TRY(G->out_rp.ensure(8 * (size_t)(G->rows_rt + nb), "batched output"));
+    }
+    SPG_TRY(spgemm_numeric(G->p2, G->sr, &T, &R, 0, R.nrows, G->c_rp.as<int64_t>(), G->c_col.as<int32_t>(), G->c_val.p));
+    P->cur = G->gs;
+    SPG_TRY(fill_i64(P, G->out_rp.as<int64_t>(), G->rows_rt + nb, 0));
+    SPG_TRY(launch(P, "batch_split", [&] {
+        k_batch_split<<<grid_for(G->rows_rt, 256), 256, 0, cs(P)>>>(d + 3 * nb, nb, G->rows_rt, G->c_rp.as<int64_t>(),
+                                                                   G->c_col.as<int32_t>(), G->out_rp.as<int64_t>());
+    }));
+    P->cur = nullptr;
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_galerkin_batched(spg_plan P, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                                              const spg_csr* A, const spg_csr* R, spg_csr* out, int32_t use_graph) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->cur = nullptr;
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    if (nb < 1 || !RT || !A || !R || !out) return fail(SPG_ERR_ARG, "need nb >= 1 and non-NULL arrays");
+    for (int b = 0; b < nb; ++b) {
+        SPG_TRY(check_csr(&RT[b], "RT", sr, true));
+        SPG_TRY(check_csr(&A[b], "A", sr, true));
+        SPG_TRY(check_csr(&R[b], "R", sr, true));
+        if (RT[b].ncols != A[b].nrows || A[b].ncols != R[b].nrows || R[b].ncols != RT[b].nrows)
+            return fail(SPG_ERR_SHAPE, "instance shapes must be RT: M x N, A: N x N', R: N' x M");
+    }
+    GalerkinState* G = galerkin_state(P);
+    if (!G) return fail(SPG_ERR_OOM, "host allocation failed");
+    if (!G->gs) {
+        HIP_TRY(hipStreamCreateWithFlags(&G->gs, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&G->ev_in, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&G->ev_out, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(G->ev_in, P->stream));
+    HIP_TRY(hipStreamWaitEvent(G->gs, G->ev_in, 0));
+    spg_status st = galerkin_run(P, G, sr, nb, RT, A, R, use_graph);
+    P->cur = nullptr;
+    HIP_TRY(hipEventRecord(G->ev_out, G->gs));
+    HIP_TRY(hipStreamWaitEvent(P->stream, G->ev_out, 0));
+    SPG_TRY(st);
+    for (int b = 0; b < nb; ++b) {
+        const BatchDesc& D = G->h_desc[3 * (size_t)nb + b];
+        out[b].nrows = D.nrows;
+        out[b].ncols = R[b].ncols;
+        out[b].nnz = G->c_base[b + 1] - G->c_base[b];
+        out[b].row_ptr = G->out_rp.as<int64_t>() + D.row_off + b;
+        out[b].col = G->c_col.as<int32_t>() + G->c_base[b];
+        out[b].val = (const char*)G->c_val.p + (size_t)G->c_base[b] * (sr == SPG_SR_OR_AND_BOOL ? 1 : 8);
+    }
+    return SPG_OK;
+}
+
+// Capture the device sequence (with the sizes of the eager call) into one
+// graph on the state's stream.
+static spg_status galerkin_capture(spg_plan P, GalerkinState* G) {
+    G->p1->frozen = G->p2->frozen = true;
+    const int32_t prof = P->opts.profile;
+    P->opts.profile = 0;  // no timing events inside the graph
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(G->gs, hipStreamCaptureModeThreadLocal));
+    spg_status st = galerkin_sequence(P, G, false);
+    hipError_t e = hipStreamEndCapture(G->gs, &g);
+    G->p1->frozen = G->p2->frozen = false;
+    P->opts.profile = prof;
+    if (st != SPG_OK) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(SPG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    G->graph = g;
+    HIP_TRY(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+    return SPG_OK;
+}
+
+static spg_status galerkin_run(spg_plan P, GalerkinState* G, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                               const spg_csr* A, const spg_csr* R, int32_t use_graph) {
+    bool same = G->valid && G->nb == nb && G->sr == sr;
+    for (int b = 0; same && b < nb; ++b)
+        same = same_csr(G->sig_rt[b], RT[b]) && same_csr(G->sig_a[b], A[b]) && same_csr(G->sig_r[b], R[b]);
+    if (!same) {
+        // sizes and offsets of the three batches and of the result
+        if (G->exec) { hipGraphExecDestroy(G->exec); G->exec = nullptr; }
+        if (G->graph) { hipGraphDestroy(G->graph); G->graph = nullptr; }
+        G->valid = false;
+        G->nb = nb;
+        G->sr = sr;
+        G->sig_rt.assign(RT, RT + nb);
+        G->sig_a.assign(A, A + nb);
+        G->sig_r.assign(R, R + nb);
+        G->h_desc.assign(4 * (size_t)nb, BatchDesc{});
+        int64_t r0 = 0, c0 = 0, z0 = 0;
+        for (int b = 0; b < nb; ++b) {  // RT_b: M x N, columns of A's batch
+            G->h_desc[b] = BatchDesc{RT[b].row_ptr, RT[b].col, RT[b].val, RT[b].nrows, r0, z0, c0};
+            r0 += RT[b].nrows; c0 += RT[b].ncols; z0 += RT[b].nnz;
+        }
+        G->rows_rt = r0; G->cols_rt = c0; G->nnz_rt = z0;
+        r0 = c0 = z0 = 0;
+        for (int b = 0; b < nb; ++b) {
+            G->h_desc[nb + b] = BatchDesc{A[b].row_ptr, A[b].col, A[b].val, A[b].nrows, r0, z0, c0};
+            r0 += A[b].nrows; c0 += A[b].ncols; z0 += A[b].nnz;
+        }
+        G->rows_a = r0; G->nnz_a = z0;
+        const int64_t cols_a = c0;
+        r0 = c0 = z0 = 0;
+        for (int b = 0; b < nb; ++b) {
+            G->h_desc[2 * nb + b] = BatchDesc{R[b].row_ptr, R[b].col, R[b].val, R[b].nrows, r0, z0, c0};
+            r0 += R[b].nrows; c0 += R[b].ncols; z0 += R[b].nnz;
+        }
+        G->rows_r = r0; G->cols_r = c0; G->nnz_r = z0;
+        if (G->rows_a != G->cols_rt || cols_a != G->rows_r)
+            return fail(SPG_ERR_SHAPE, "batch dimension totals differ");
+        r0 = c0 = 0;
+        for (int b = 0; b < nb; ++b) {  // result: M_b x M_b, rows/columns of the coarse batch
+            G->h_desc[3 * nb + b] = BatchDesc{nullptr, nullptr, nullptr, RT[b].nrows, r0, 0, c0};
+            r0 += RT[b].nrows; c0 += R[b].ncols;
+        }
+        if (G->rows_rt >= (1ll << 31) || G->cols_rt >= (1ll << 31) || G->rows_r >= (1ll << 31) || G->cols_r >= (1ll << 31))
+            return fail(SPG_ERR_INDEX_RANGE, "batch dimensions >= 2^31");
+        const size_t w = sr == SPG_SR_OR_AND_BOOL ? 1 : 8;
+        SPG_TRY(G->desc.ensure(sizeof(BatchDesc) * 4 * (size_t)nb, "batch descriptors"));
+        SPG_TRY(G->rt_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched RT"));
+        SPG_TRY(G->rt_col.ensure(4 * (size_t)std::max<int64_t>(G->nnz_rt, 1), "batched RT"));
+        SPG_TRY(G->rt_val.ensure(w * (size_t)std::max<int64_t>(G->nnz_rt, 1), "batched RT"));
+        SPG_TRY(G->a_rp.ensure(8 * (size_t)(G->rows_a + 1), "batched A"));
+        SPG_TRY(G->a_col.ensure(4 * (size_t)std::max<int64_t>(G->nnz_a, 1), "batched A"));
+        SPG_TRY(G->a_val.ensure(w * (size_t)std::max<int64_t>(G->nnz_a, 1), "batched A"));
+        SPG_TRY(G->r_rp.ensure(8 * (size_t)(G->rows_r + 1), "batched R"));
+        SPG_TRY(G->r_col.ensure(4 * (size_t)std::max<int64_t>(G->nnz_r, 1), "batched R"));
+        SPG_TRY(G->r_val.ensure(w * (size_t)std::max<int64_t>(G->nnz_r, 1), "batched R"));
+        HIP_TRY(hipMemcpyAsync(G->desc.p, G->h_desc.data(), sizeof(BatchDesc) * 4 * (size_t)nb, hipMemcpyHostToDevice,
+                               G->gs));
+        if (!G->p1) SPG_TRY(spg_plan_create(&G->p1, (void*)G->gs, &P->opts));
+        if (!G->p2) SPG_TRY(spg_plan_create(&G->p2, (void*)G->gs, &P->opts));
+        G->p1->opts = G->p2->opts = P->opts;
+        G->p1->stream = G->p2->stream = G->gs;
+        G->p1->opts.profile = G->p2->opts.profile = 0;
+        G->p1->frozen = G->p2->frozen = false;
+        SPG_TRY(galerkin_sequence(P, G, true));
+        // first entry of each instance in C (host copy of the row pointers)
+        std::vector<int64_t> crp((size_t)G->rows_rt + 1);
+        HIP_TRY(hipMemcpyAsync(crp.data(), G->c_rp.p, 8 * crp.size(), hipMemcpyDeviceToHost, G->gs));
+        HIP_TRY(hipStreamSynchronize(G->gs));
+        G->c_base.resize((size_t)nb + 1);
+        for (int b = 0; b < nb; ++b) G->c_base[b] = crp[(size_t)G->h_desc[3 * nb + b].row_off];
+        G->c_base[nb] = crp[(size_t)G->rows_rt];
+        G->valid = true;
+        if (use_graph) SPG_TRY(galerkin_capture(P, G));  // for later calls; this one ran eagerly
+    } else if (use_graph) {
+        if (!G->exec) SPG_TRY(galerkin_capture(P, G));
+        HIP_TRY(hipGraphLaunch(G->exec, G->gs));
+    } else {
+        G->p1->frozen = G->p2->frozen = true;
+        spg_status st = galerkin_sequence(P, G, false);
+        G->p1->frozen = G->p2->frozen = false;
+        SPG_TRY(st);
+    }
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_galerkin_copy(spg_plan P, int64_t* row_ptr, int32_t* col, void* val) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    GalerkinState* G = galerkin_state(P);
+    if (!G || !G->valid) return fail(SPG_ERR_STATE, "no batched Galerkin result on this plan");
+    const size_t w = G->sr == SPG_SR_OR_AND_BOOL ? 1 : 8;
+    if (!row_ptr) return fail(SPG_ERR_ARG, "row_ptr is NULL");
+    HIP_TRY(hipMemcpyAsync(row_ptr, G->out_rp.p, 8 * (size_t)(G->rows_rt + G->nb), hipMemcpyDeviceToDevice, P->stream));
+    if (G->nnz_c > 0) {
+        if (!col) return fail(SPG_ERR_ARG, "col is NULL");
+        HIP_TRY(hipMemcpyAsync(col, G->c_col.p, 4 * (size_t)G->nnz_c, hipMemcpyDeviceToDevice, P->stream));
+        if (val) HIP_TRY(hipMemcpyAsync(val, G->c_val.p, w * (size_t)G->nnz_c, hipMemcpyDeviceToDevice, P->stream));
+    }
+    return SPG_OK;
+}
+
+// per-plan Galerkin state (kept beside the plan, freed with it)
+#include <map>
+static std::map<spg_plan, GalerkinState*>& galerkin_map() {
+    static std::map<spg_plan, GalerkinState*> m;
+    return m;
+}
+static GalerkinState* galerkin_state(spg_plan P) {
+    auto& m = galerkin_map();
+    auto it = m.find(P);
+    if (it != m.end()) return it->second;
+    GalerkinState* G = new (std::nothrow) GalerkinState();
+    if (G) m[P] = G;
+    return G;
+}
+static void galerkin_free(GalerkinState* G) {
+    if (!G) return;
+    if (G->exec) hipGraphExecDestroy(G->exec);
+    if (G->graph) hipGraphDestroy(G->graph);
+    for (DevBuf* b : {&G->desc, &G->rt_rp, &G->rt_col, &G->rt_val, &G->a_rp, &G->a_col, &G->a_val, &G->r_rp, &G->r_col,
+                      &G->r_val, &G->t_rp, &G->t_col, &G->t_val, &G->c_rp, &G->c_col, &G->c_val, &G->out_rp})
+        b->release();
+    if (G->p1) spg_plan_destroy(G->p1);
+    if (G->p2) spg_plan_destroy(G->p2);
+    if (G->gs) {
+        hipStreamSynchronize(G->gs);
+        hipStreamDestroy(G->gs);
+    }
+    if (G->ev_in) hipEventDestroy(G->ev_in);
+    if (G->ev_out) hipEventDestroy(G->ev_out);
+    delete G;
+}
+void spg_release_galerkin(spg_plan P) {
+    auto& m = galerkin_map();
+    auto it = m.find(P);
+    if (it == m.end()) return;
+    galerkin_free(it->second);
+    m.erase(it);
 }
