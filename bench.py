@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (3 times), the reference for "
                          "scaling the HBM byte counters")
+    ap.add_argument("--mode", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the headline product (default); c3, c4, c5: only that secondary "
+                         "workload, with its per-kernel times (for profiling)")
     return ap.parse_args()
 
 
@@ -168,7 +171,7 @@ def learned_modes(A2, dA2, args):
     return res
 
 
-def batched_modes(args):
+def batched_modes(args, reps=20):
     """64 AMG Galerkin products (R^T A) R, A = 7-point Poisson on N^3 grids
     with N uniform in [16, 64], R = 2x2x2 aggregation: one batched call
     replayed as a HIP graph, the same batched call without the graph, and
@@ -186,7 +189,6 @@ def batched_modes(args):
     plan = spg.Plan()
     res = spg.spgemm_galerkin_batched(plan, "f64", rts, As, Rs, use_graph=True)
     flops += sum(int(n) for n in _t_nnz(plan, rts, As))  # flops(T, R) = nnz(T): one entry per row of R
-    reps = 20
     t_graph, _ = _time(lambda: spg.spgemm_galerkin_batched(plan, "f64", rts, As, Rs, use_graph=True), reps)
     plan_e = spg.Plan()
     spg.spgemm_galerkin_batched(plan_e, "f64", rts, As, Rs, use_graph=False)
@@ -223,7 +225,7 @@ def _t_nnz(plan, rts, As):
     return out
 
 
-def layered_modes(args):
+def layered_modes(args, profile=False):
     """Split-3D layer shape: ER scale 18, edge factor 16; the inner dimension
     in c contiguous layers, C_l = A(:,K_l) B(K_l,:), then the merge."""
     import torch
@@ -234,9 +236,12 @@ def layered_modes(args):
     B = synth.rmat(18, 16, synth.ER, seed=4)
     dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
     dB = spg.DeviceCSR.from_arrays(B.nrows, B.ncols, B.row_ptr, B.col, B.val)
-    plan = spg.Plan()
+    plan = spg.Plan(profile=profile)
     t_full, C = _time(lambda: spg.spgemm(plan, "f64", dA, dB), 3)
     flops = plan.stats()["flops"]
+    if profile:
+        unsplit_kernels = kernel_table(plan, 4)
+        plan.profile_reset()
     out = {"workload": "ER (.25,.25,.25,.25) scale 18 edge factor 16, A*B FP64", "flops": flops,
            "nnz_c": C.nnz, "unsplit": {"ms": round(t_full, 4), "gflops": round(2.0 * flops / t_full / 1e6, 3)}}
     for c in (4, 16):
@@ -250,21 +255,72 @@ def layered_modes(args):
             return layers
 
         t_prod, _ = _time(products, 3)
+        if profile:
+            prod_kernels = kernel_table(plan, 4)
+            plan.profile_reset()
         t_merge, M = _time(lambda: spg.spgemm_merge_layers(plan, "f64", layers), 3)
         assert M.nnz == C.nnz
         out["c%d" % c] = {"layers_ms": round(t_prod, 4), "merge_ms": round(t_merge, 4),
                           "gflops_layers": round(2.0 * flops / t_prod / 1e6, 3),
                           "layer_nnz": sum(L.nnz for L in layers)}
+        if profile:
+            out["c%d" % c]["layer_kernels"] = prod_kernels
+            out["c%d" % c]["merge_kernels"] = kernel_table(plan, 4)
+            plan.profile_reset()
         del layers
+    if profile:
+        out["unsplit_kernels"] = unsplit_kernels
     plan.close()
     torch.cuda.empty_cache()
     return out
+
+
+def kernel_table(plan, steps):
+    out = {}
+    for name, (launches, total) in plan.profile_read().items():
+        out[name] = {"launches_per_step": launches / steps, "ms_per_step": round(total / steps, 4)}
+    return dict(sorted(out.items(), key=lambda kv: -kv[1]["ms_per_step"]))
+
+
+def secondary_mode(args):
+    """One secondary workload alone: c3 (layers + merge), c4 (batched
+    Galerkin), c5 (R-MAT scale 19 product)."""
+    import torch
+
+    import paper_1510_00844_amd as spg
+    import synth
+    torch.cuda.set_device(0)
+    out = {"mode": args.mode}
+    if args.mode == "c4":
+        out.update(batched_modes(args, reps=args.steps))
+    elif args.mode == "c3":
+        out.update(layered_modes(args, profile=True))
+    else:
+        A = synth.rmat(19, 16, synth.G500, seed=6)
+        dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
+        plan = spg.Plan(profile=True, dense_chunk_cols=args.dense_cols, streams=args.streams)
+        for _ in range(args.warmup):
+            spg.spgemm(plan, "f64", dA, dA, values=True)
+        torch.cuda.synchronize()
+        plan.profile_reset()
+        t, C = _time(lambda: spg.spgemm(plan, "f64", dA, dA), args.steps)
+        flops = plan.stats()["flops"]
+        st = plan.stats()
+        out.update({"workload": "R-MAT G500 scale 19 edge factor 16, A*A FP64 two-phase", "ms": round(t, 4),
+                    "gflops": round(2.0 * flops / t / 1e6, 3), "flops": flops, "nnz_c": C.nnz,
+                    "num_rows": st["num_rows"], "sym_rows": st["sym_rows"],
+                    "kernels": kernel_table(plan, args.steps + 1)})
+        plan.close()
+    print(json.dumps(out))
 
 
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.mode != "c2":
+        secondary_mode(args)
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "

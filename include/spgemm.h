@@ -85,7 +85,15 @@ typedef struct {
     int32_t unroll;            /* numeric heavy rows: gathers in flight per lane (4 or 8) */
     int32_t sym_gather_map;    /* the same two choices for the symbolic bitmap rows */
     int32_t sym_unroll;
-    int32_t reserved[5];
+    int32_t chunk_min_nnz;     /* numeric rows whose bitmap was saved by the symbolic pass and that have
+                                  more than this many outputs take column-chunk work items instead of
+                                  a hash table (1..hash_max_nnz) */
+    int32_t chunk_group;       /* most column chunks one such work item spans (1..128; the LDS may
+                                  allow fewer) */
+    int32_t rank_max_nnz;      /* numeric rows with a saved bitmap and at most this many outputs
+                                  accumulate the whole row in one workgroup (capacities 4096, 8192,
+                                  16384 as the LDS allows; below 4096: never) */
+    int32_t reserved[2];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;

@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
                 ("dense_chunk_cols", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("gather_map", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("sym_gather_map", ctypes.c_int32), ("sym_unroll", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("chunk_min_nnz", ctypes.c_int32), ("chunk_group", ctypes.c_int32),
+                ("rank_max_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -163,7 +164,8 @@ class Plan:
 
     def __init__(self, device=None, stream: Optional[torch.cuda.Stream] = None, validate=False,
                  profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
-                 dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0):
+                 dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0,
+                 chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0):
         L = lib()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
@@ -175,7 +177,9 @@ class Plan:
             for name, v in (("small_max_flops", small_max_flops), ("hash_max_flops", hash_max_flops),
                             ("hash_max_nnz", hash_max_nnz), ("dense_chunk_cols", dense_chunk_cols),
                             ("streams", streams), ("gather_map", gather_map), ("unroll", unroll),
-                            ("sym_gather_map", sym_gather_map), ("sym_unroll", sym_unroll)):
+                            ("sym_gather_map", sym_gather_map), ("sym_unroll", sym_unroll),
+                            ("chunk_min_nnz", chunk_min_nnz), ("chunk_group", chunk_group),
+                            ("rank_max_nnz", rank_max_nnz)):
                 if v:
                     setattr(o, name, int(v))
             h = ctypes.c_void_p()

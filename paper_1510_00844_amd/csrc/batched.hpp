@@ -21,8 +21,10 @@ struct BatchDesc {
     int64_t col_off;  // first column of the instance in the batch
 };
 
+// Largest b with d[b].row_off <= r (instances with no rows share the
+// offset of the next instance and are skipped).
 __device__ inline int find_instance(const BatchDesc* d, int32_t nb, int64_t r) {
-    int lo = 0, hi = nb;  // largest b with row_off <= r
+    int lo = 0, hi = nb;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
         if (d[mid].row_off <= r) lo = mid; else hi = mid;
@@ -30,26 +32,37 @@ __device__ inline int find_instance(const BatchDesc* d, int32_t nb, int64_t r) {
     return lo;
 }
 
-// One thread per batch row: shifted row pointer and the row's entries.
+// Largest b with d[b].nz_off <= e: the instance holding batch entry e.
+__device__ inline int find_instance_nz(const BatchDesc* d, int32_t nb, int64_t e) {
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (d[mid].nz_off <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Grid-stride over x < max(rows + 1, nnz): row pointer x (shifted by the
+// entries before its instance) and entry x (column shifted by the columns
+// before its instance, value copied), so reads and writes are coalesced.
 // vw = value bytes (8 or 1; 0 = no values).
 __global__ void __launch_bounds__(256) k_batch_assemble(const BatchDesc* d, int32_t nb, int64_t rows, int64_t nnz,
                                                         int32_t vw, int64_t* rp, int32_t* col, void* val) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r > rows) return;
-    if (r == rows) {
-        rp[rows] = nnz;
-        return;
-    }
-    const int b = find_instance(d, nb, r);
-    const BatchDesc& D = d[b];
-    const int64_t i = r - D.row_off;
-    const int64_t s = D.rp[i], e = D.rp[i + 1];
-    const int64_t o = D.nz_off - D.rp[0];
-    rp[r] = o + s;
-    for (int64_t p = s; p < e; ++p) {
-        col[o + p] = (int32_t)(D.col[p] + D.col_off);
-        if (vw == 8) ((uint64_t*)val)[o + p] = ((const uint64_t*)D.val)[p];
-        else if (vw == 1) ((uint8_t*)val)[o + p] = D.val ? ((const uint8_t*)D.val)[p] : (uint8_t)1;
+    const int64_t n = rows + 1 > nnz ? rows + 1 : nnz;
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256) {
+        if (x < rows) {
+            const BatchDesc& D = d[find_instance(d, nb, x)];
+            rp[x] = D.nz_off + (D.rp[x - D.row_off] - D.rp[0]);
+        } else if (x == rows) {
+            rp[rows] = nnz;
+        }
+        if (x < nnz) {
+            const BatchDesc& D = d[find_instance_nz(d, nb, x)];
+            const int64_t e = x - D.nz_off + D.rp[0];
+            col[x] = (int32_t)(D.col[e] + D.col_off);
+            if (vw == 8) ((uint64_t*)val)[x] = ((const uint64_t*)D.val)[e];
+            else if (vw == 1) ((uint8_t*)val)[x] = D.val ? ((const uint8_t*)D.val)[e] : (uint8_t)1;
+        }
     }
 }
 

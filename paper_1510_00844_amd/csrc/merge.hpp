@@ -3,11 +3,12 @@
 // output is the sorted union of the c sorted segments layer_l(i,:), with
 // values of equal columns combined in ascending layer order.  The paper
 // merges triples with a size-c heap per thread; here a row is merged by a
-// wave (<= 64 entries in all layers), a workgroup (<= 4096 entries: LDS
-// bitonic sort of (column, position) keys, positions taken layer by layer so
-// ties keep layer order), or, for longer rows, a workgroup sweeping column
-// chunks with an LDS dense accumulator, each layer's chunk range found by
-// binary search (the column-range split of Section 4.3).
+// wave (<= 64 entries in all layers: register sort), a workgroup (<= 4096
+// entries: each entry's place in the merged order from binary searches in
+// the other layers' segments, staged in LDS), or, for longer rows, a
+// workgroup sweeping column chunks with an LDS dense accumulator, each
+// layer's chunk range found by binary search (the column-range split of
+// Section 4.3).
 #pragma once
 #include "products.hpp"
 #include "rowinfo.hpp"
@@ -20,8 +21,20 @@ struct LayerDesc {
     const void* val;
 };
 
-constexpr int MBIN_EMPTY = 0, MBIN_SMALL = 1, MBIN_LDS = 2, MBIN_DENSE = 3;
+// merge bins by total row length L over the layers
+constexpr int MBIN_EMPTY = 0, MBIN_SMALL = 1, MBIN_R256 = 2, MBIN_R1K = 3, MBIN_R4K = 4, MBIN_DENSE = 5;
+constexpr int MBINS = 6;
 constexpr int MERGE_LDS_MAX = 4096;
+constexpr int MERGE_MAX_LAYERS = 64;
+
+__device__ inline int merge_bin(int64_t L) {
+    if (L == 0) return MBIN_EMPTY;
+    if (L <= SPG_WAVE) return MBIN_SMALL;
+    if (L <= 256) return MBIN_R256;
+    if (L <= 1024) return MBIN_R1K;
+    if (L <= MERGE_LDS_MAX) return MBIN_R4K;
+    return MBIN_DENSE;
+}
 
 __global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, const LayerDesc* layers,
                                                        int64_t* total_len, uint8_t* bin,
@@ -38,7 +51,7 @@ __global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, con
         int64_t L = 0;
         for (int l = 0; l < c; ++l) L += layers[l].rp[i + 1] - layers[l].rp[i];
         total_len[i] = L;
-        int b = L == 0 ? MBIN_EMPTY : (L <= SPG_WAVE ? MBIN_SMALL : (L <= MERGE_LDS_MAX ? MBIN_LDS : MBIN_DENSE));
+        int b = merge_bin(L);
         bin[i] = (uint8_t)b;
         atomicAdd(&s_hist[b], 1);
         atomicAdd((unsigned long long*)&s_len[b], (unsigned long long)L);
@@ -107,66 +120,121 @@ __global__ void __launch_bounds__(256) k_merge_small(int32_t c, const LayerDesc*
     }
 }
 
+// first index in [lo, hi) of the sorted s with s[idx] >= x (lower) or > x (upper)
+__device__ inline int seg_lower(const int32_t* s, int lo, int hi, int32_t x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ inline int seg_upper(const int32_t* s, int lo, int hi, int32_t x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+// layer of staged entry x: largest l < c with soff[l] <= x
+__device__ inline int layer_of(const int32_t* soff, int c, int x) {
+    int lo = 0, hi = c;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (soff[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// One workgroup per row of 65..cap entries.  The row's c segments are
+// staged back to back in LDS (scol).  Count pass: an entry opens a new
+// column unless an earlier layer holds the same column.  Fill pass: the
+// entry's place in the merged order is its index in its own segment plus,
+// for every other layer, the entries of that layer with smaller columns
+// (and, for earlier layers, equal ones), so equal columns end up adjacent in
+// ascending layer order; the runs are then folded left to right.
+// Dynamic LDS: cap values (fill pass), cap staged columns, cap merged
+// columns (fill pass).
 template <int SR, int NT>
-__global__ void __launch_bounds__(NT) k_merge_lds(int32_t c, const LayerDesc* layers,
-                                                  const int32_t* rows, const int64_t* total_len,
-                                                  int64_t* cnt, const int64_t* out_rp,
-                                                  int32_t* out_col, void* out_val) {
+__global__ void __launch_bounds__(NT) k_merge_rank(int32_t c, const LayerDesc* layers, const int32_t* rows,
+                                                   const int64_t* total_len, int32_t cap, int64_t* cnt,
+                                                   const int64_t* out_rp, int32_t* out_col, void* out_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
-    constexpr int LMAX = MERGE_LDS_MAX;
-    constexpr int PER = LMAX / NT;
-    __shared__ uint64_t keys[LMAX];
-    __shared__ V vals[LMAX];
+    extern __shared__ uint64_t dyn[];
+    V* mval = reinterpret_cast<V*>(dyn);
+    int32_t* scol = cnt ? reinterpret_cast<int32_t*>(dyn) : reinterpret_cast<int32_t*>(mval + cap);
+    int32_t* mcol = scol + cap;
+    __shared__ int32_t soff[MERGE_MAX_LAYERS + 1];
+    __shared__ int64_t srs[MERGE_MAX_LAYERS];
     __shared__ int32_t red[NT / SPG_WAVE + 1];
     const int64_t i = rows[blockIdx.x];
     const int L = (int)total_len[i];
-    int P = 1;
-    while (P < L) P <<= 1;
-    int pos = 0;
-    for (int l = 0; l < c; ++l) {
-        const int64_t rs = layers[l].rp[i];
-        const int len = (int)(layers[l].rp[i + 1] - rs);
-        for (int t = threadIdx.x; t < len; t += NT) {
-            const int idx = pos + t;
-            keys[idx] = ((uint64_t)(uint32_t)layers[l].col[rs + t] << 12) | (uint64_t)idx;
-            if (!cnt) vals[idx] = S::load(layers[l].val, rs + t);
+    if (threadIdx.x < SPG_WAVE) {  // c <= 64 segment lengths, scanned by one wave
+        const int l = threadIdx.x;
+        int len = 0;
+        if (l < c) {
+            const int64_t rs = layers[l].rp[i];
+            len = (int)(layers[l].rp[i + 1] - rs);
+            srs[l] = rs;
         }
-        pos += len;
+        const int incl = wave_inclusive_scan_add(len);
+        if (l < c) soff[l + 1] = incl;
+        if (l == 0) soff[0] = 0;
     }
-    for (int t = L + threadIdx.x; t < P; t += NT) keys[t] = ~0ull;
     __syncthreads();
-    block_bitonic_sort_u64<NT>(keys, P);
-    // heads over positions [t*PER, (t+1)*PER)
-    int32_t mine = 0;
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-        const int x = threadIdx.x * PER + s;
-        if (x < L) {
-            const uint64_t col = keys[x] >> 12;
-            mine += (x == 0 || (keys[x - 1] >> 12) != col) ? 1 : 0;
-        }
+    for (int x = threadIdx.x; x < L; x += NT) {
+        const int l = layer_of(soff, c, x);
+        scol[x] = layers[l].col[srs[l] + (x - soff[l])];
     }
-    int32_t heads_total;
-    int32_t rank = block_exclusive_scan<NT, int32_t>(mine, &heads_total, red);
+    __syncthreads();
     if (cnt) {
-        if (threadIdx.x == 0) cnt[i] = heads_total;
+        int32_t mine = 0;
+        for (int x = threadIdx.x; x < L; x += NT) {
+            const int l = layer_of(soff, c, x);
+            const int32_t col = scol[x];
+            bool fresh = true;
+            for (int l2 = 0; l2 < l && fresh; ++l2) {
+                const int q = seg_lower(scol, soff[l2], soff[l2 + 1], col);
+                fresh = !(q < soff[l2 + 1] && scol[q] == col);
+            }
+            mine += fresh ? 1 : 0;
+        }
+        const int32_t tot = block_reduce_add<NT, int32_t>(mine, red);
+        if (threadIdx.x == 0) cnt[i] = tot;
         return;
     }
+    for (int x = threadIdx.x; x < L; x += NT) {
+        const int l = layer_of(soff, c, x);
+        const int32_t col = scol[x];
+        int pos = x - soff[l];
+        for (int l2 = 0; l2 < c; ++l2) {
+            if (l2 == l) continue;
+            const int lo = soff[l2], hi = soff[l2 + 1];
+            pos += (l2 < l ? seg_upper(scol, lo, hi, col) : seg_lower(scol, lo, hi, col)) - lo;
+        }
+        mcol[pos] = col;
+        if (out_val) mval[pos] = S::load(layers[l].val, srs[l] + (x - soff[l]));
+    }
+    __syncthreads();
+    // heads over a contiguous range of merged positions per thread
+    const int per = (L + NT - 1) / NT;
+    const int q0 = threadIdx.x * per;
+    const int q1 = q0 + per < L ? q0 + per : L;
+    int32_t mine = 0;
+    for (int q = q0; q < q1; ++q) mine += (q == 0 || mcol[q - 1] != mcol[q]) ? 1 : 0;
+    int32_t total;
+    int32_t rank = block_exclusive_scan<NT, int32_t>(mine, &total, red);
     const int64_t o = out_rp[i];
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-        const int x = threadIdx.x * PER + s;
-        if (x < L) {
-            const uint64_t col = keys[x] >> 12;
-            if (x == 0 || (keys[x - 1] >> 12) != col) {
-                V acc = vals[keys[x] & 0xfff];
-                for (int y = x + 1; y < L && (keys[y] >> 12) == col; ++y)
-                    acc = S::add(acc, vals[keys[y] & 0xfff]);
-                out_col[o + rank] = (int32_t)col;
-                if (out_val) S::store(out_val, o + rank, acc);
-                ++rank;
+    for (int q = q0; q < q1; ++q) {
+        if (q == 0 || mcol[q - 1] != mcol[q]) {
+            const int32_t col = mcol[q];
+            out_col[o + rank] = col;
+            if (out_val) {
+                V acc = mval[q];
+                for (int y = q + 1; y < L && mcol[y] == col; ++y) acc = S::add(acc, mval[y]);
+                S::store(out_val, o + rank, acc);
             }
+            ++rank;
         }
     }
 }

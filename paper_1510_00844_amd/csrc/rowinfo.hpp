@@ -20,6 +20,7 @@ struct BinParams {
     int32_t dense_ok;         // symbolic LDS bitmap allowed (n <= 2^19)
     int32_t rank_max_log2;    // numeric rank-space accumulator: largest capacity (log2), 0 = off
     int32_t chunk_counts;     // the bitmap pass records per-chunk counts for the numeric chunks
+    int32_t chunk_min_nnz;    // rows with chunk counts and more outputs than this take rank chunks
     int64_t ncols;            // n
 };
 
@@ -64,10 +65,10 @@ __device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, bool sym
         if (lg < RANK_MIN_LOG2) lg = RANK_MIN_LOG2;
         return BIN_RANK0 + (lg - RANK_MIN_LOG2);
     }
-    // rows with a saved bitmap take its rank chunks once a hash table would
-    // need the largest size (one workgroup per CU)
+    // rows with a saved bitmap and chunk counts may take rank chunks before
+    // the largest hash tables
     const bool chunks_ok = sym_dense && bp.chunk_counts;
-    const int64_t hash_lim = chunks_ok && bp.hash_max_nnz > 2048 ? 2048 : bp.hash_max_nnz;
+    const int64_t hash_lim = chunks_ok ? bp.chunk_min_nnz : bp.hash_max_nnz;
     if (cnt <= hash_lim) {
         int lg = ceil_log2_i64(2 * cnt);
         if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
@@ -124,7 +125,12 @@ __device__ inline void flush_stats(const RowInfoOut& o, int* s_hist, int64_t* s_
     }
 }
 
-// 256 threads = 16 groups of 16 lanes, one row per group.
+__device__ inline void rowinfo_row(const Csr& A, const Csr& B, int64_t k_lo, int64_t k_hi, int full_window,
+                                   const BinParams& bp, const RowInfoOut& o, int64_t i, int gl, int* s_hist,
+                                   int64_t* s_flops, int64_t* s_annz);
+
+// 256 threads = 16 groups of 16 lanes, one row per group; the grid strides
+// over groups of 16 rows (few workgroups, so few global statistics atomics).
 __global__ void __launch_bounds__(256) k_rowinfo(Csr A, Csr B, int64_t k_lo, int64_t k_hi,
                                                  int full_window, BinParams bp, RowInfoOut o) {
     __shared__ int s_hist[NBINS];
@@ -136,7 +142,15 @@ __global__ void __launch_bounds__(256) k_rowinfo(Csr A, Csr B, int64_t k_lo, int
     }
     __syncthreads();
     const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
-    const int64_t i = (int64_t)blockIdx.x * 16 + g;
+    for (int64_t i0 = (int64_t)blockIdx.x * 16; i0 < A.nrows; i0 += (int64_t)gridDim.x * 16)
+        rowinfo_row(A, B, k_lo, k_hi, full_window, bp, o, i0 + g, gl, s_hist, s_flops, s_annz);
+    __syncthreads();
+    flush_stats(o, s_hist, s_flops, s_annz);
+}
+
+__device__ inline void rowinfo_row(const Csr& A, const Csr& B, int64_t k_lo, int64_t k_hi, int full_window,
+                                   const BinParams& bp, const RowInfoOut& o, int64_t i, int gl, int* s_hist,
+                                   int64_t* s_flops, int64_t* s_annz) {
     bool active = i < A.nrows;
     int64_t beg = 0, end = 0;
     if (active) {
@@ -173,8 +187,6 @@ __global__ void __launch_bounds__(256) k_rowinfo(Csr A, Csr B, int64_t k_lo, int
         mb = o2 > mb ? o2 : mb;
     }
     if (active && gl == 0) finish_row(i, beg, end, f, mb, bp, o, s_hist, s_flops, s_annz);
-    __syncthreads();
-    flush_stats(o, s_hist, s_flops, s_annz);
 }
 
 // One 256-thread workgroup per queued long row, grid-stride over the queue.

@@ -229,6 +229,9 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->sym_gather_map = 2;
     o->sym_unroll = 8;
     o->dense_chunk_cols = 4096;
+    o->chunk_min_nnz = 4096;
+    o->chunk_group = 128;
+    o->rank_max_nnz = 16384;
 }
 
 extern "C" const char* spg_status_string(spg_status s) {
@@ -298,6 +301,9 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         if (!P->opts.unroll) P->opts.unroll = d.unroll;
         if (!P->opts.sym_gather_map) P->opts.sym_gather_map = d.sym_gather_map;
         if (!P->opts.sym_unroll) P->opts.sym_unroll = d.sym_unroll;
+        if (!P->opts.chunk_min_nnz) P->opts.chunk_min_nnz = P->opts.hash_max_nnz;
+        if (!P->opts.chunk_group) P->opts.chunk_group = d.chunk_group;
+        if (!P->opts.rank_max_nnz) P->opts.rank_max_nnz = d.rank_max_nnz;
     }
     auto map_ok = [](int m) { return m == 1 || m == 2; };
     auto unroll_ok = [](int u) { return u == 4 || u == 8; };
@@ -317,6 +323,11 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 4096) {
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
+    }
+    if (P->opts.chunk_min_nnz < 1 || P->opts.chunk_min_nnz > P->opts.hash_max_nnz || P->opts.chunk_group < 1 ||
+        P->opts.chunk_group > MAX_CHUNKS) {
+        delete P;
+        return fail(SPG_ERR_ARG, "chunk_min_nnz must be in [1, hash_max_nnz], chunk_group in [1, 128]");
     }
     if (P->opts.dense_chunk_cols != 16384 && P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096) {
         delete P;
@@ -501,6 +512,7 @@ static BinParams bin_params(spg_plan P, int64_t n) {
     bp.small_max_flops = P->opts.small_max_flops;
     bp.hash_max_flops = P->opts.hash_max_flops;
     bp.hash_max_nnz = P->opts.hash_max_nnz;
+    bp.chunk_min_nnz = P->opts.chunk_min_nnz;
     const int64_t bitmap_bytes = ((n + 31) / 32) * 4;
     // dense_ok: one LDS bitmap covers all n columns (the bitmap pass then
     // counts in one block and can save the bitmap for the numeric pass)
@@ -514,7 +526,7 @@ static BinParams bin_params(spg_plan P, int64_t n) {
     if (bp.dense_ok) {
         const int64_t words = 2 * bitmap_bytes;
         for (int lg = 14; lg >= RANK_MIN_LOG2; --lg)
-            if (words + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) {
+            if ((1ll << lg) <= P->opts.rank_max_nnz && words + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) {
                 bp.rank_max_log2 = lg;
                 break;
             }
@@ -580,7 +592,7 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                  P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr};
     if (m > 0) {
         SPG_TRY(launch(P, "rowinfo", [&] {
-            k_rowinfo<<<grid_for(m, 16), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
+            k_rowinfo<<<(unsigned)std::min<int64_t>(grid_for(m, 16), 4096), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "rowinfo_long", [&] {
             k_rowinfo_long<<<256, 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
@@ -770,7 +782,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             // an item holds at least one whole chunk (<= W outputs); group as
             // many chunks as the LDS allows, up to RANKC_GROUP
             const int32_t RC = std::max(RANKC_CAP, W);
-            int32_t G = std::min<int32_t>(chunks, MAX_CHUNKS);
+            int32_t G = std::min<int32_t>(chunks, P->opts.chunk_group);
             while (G > 1 && (int64_t)G * (W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) --G;
             SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(nr * chunks, 1), "rank items"));
             SPG_TRY(P->small_i32.ensure(64 * 4, "counters"));
@@ -889,11 +901,12 @@ extern "C" spg_status spgemm_numeric(spg_plan P, spg_semiring sr, const spg_csr*
 template <int SR>
 static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, const int64_t* orp, int32_t* ocol,
                                void* oval) {
+    typedef typename Sr<SR>::acc_t V;
     const LayerDesc* d = P->layer_desc.as<LayerDesc>();
     const int32_t* lists = P->mlists.as<int32_t>();
     const int64_t* tl = P->merge_len.as<int64_t>();
     int64_t off = 0;
-    for (int bb = 0; bb < 4; ++bb) {
+    for (int bb = 0; bb < MBINS; ++bb) {
         const int64_t nr = P->merge_counts[bb];
         const int32_t* rows = lists + off;
         off += nr;
@@ -902,14 +915,23 @@ static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, c
             SPG_TRY(launch(P, "merge_small", [&] {
                 k_merge_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, d, rows, (int32_t)nr, cnt, orp, ocol, oval);
             }));
-        } else if (bb == MBIN_LDS) {
-            SPG_TRY(launch(P, "merge_lds", [&] {
-                k_merge_lds<SR, 256><<<(unsigned)nr, 256, 0, cs(P)>>>(c, d, rows, tl, cnt, orp, ocol, oval);
-            }));
-        } else {
+        } else if (bb == MBIN_DENSE) {
             SPG_TRY(launch(P, "merge_dense", [&] {
                 k_merge_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, cs(P)>>>(c, d, rows, n, cnt, orp, ocol, oval);
             }));
+        } else {
+            const int32_t cap = bb == MBIN_R256 ? 256 : (bb == MBIN_R1K ? 1024 : MERGE_LDS_MAX);
+            const size_t lds = cnt ? (size_t)cap * 4 : (size_t)cap * (8 + sizeof(V));
+            const std::string name = "merge_rank" + std::to_string(cap);
+            if (cap == 256) {
+                SPG_TRY(launch(P, name, [&] {
+                    k_merge_rank<SR, 64><<<(unsigned)nr, 64, lds, cs(P)>>>(c, d, rows, tl, cap, cnt, orp, ocol, oval);
+                }));
+            } else {
+                SPG_TRY(launch(P, name, [&] {
+                    k_merge_rank<SR, 256><<<(unsigned)nr, 256, lds, cs(P)>>>(c, d, rows, tl, cap, cnt, orp, ocol, oval);
+                }));
+            }
         }
     }
     return SPG_OK;
@@ -1268,7 +1290,7 @@ extern "C" spg_status spgemm_learned_run(spg_plan P, spg_semiring sr, const spg_
     lp.hash_max_nnz = P->opts.hash_max_nnz;
     if (m > 0) {
         SPG_TRY(launch(P, "rowinfo", [&] {
-            k_rowinfo<<<grid_for(m, 16), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
+            k_rowinfo<<<(unsigned)std::min<int64_t>(grid_for(m, 16), 4096), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "rowinfo_long", [&] {
             k_rowinfo_long<<<256, 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
@@ -1443,6 +1465,10 @@ static bool same_csr(const spg_csr& x, const spg_csr& y) {
            x.val == y.val;
 }
 
+static unsigned assemble_grid(int64_t rows, int64_t nnz) {
+    return (unsigned)std::min<int64_t>(grid_for(std::max(rows + 1, nnz), 256), 8192);
+}
+
 // The whole device sequence of one batched call.  eager: may allocate and
 // read sizes back; otherwise (graph capture) only launches, with the sizes
 // of the eager call.
@@ -1455,17 +1481,17 @@ static spg_status galerkin_sequence(spg_plan P, GalerkinState* G, bool eager) {
     // eager call may synchronize
     G->p1->opts.validate = G->p2->opts.validate = eager ? P->opts.validate : 0;
     SPG_TRY(launch(P, "batch_assemble", [&] {
-        k_batch_assemble<<<grid_for(G->rows_rt + 1, 256), 256, 0, cs(P)>>>(d, nb, G->rows_rt, G->nnz_rt, vw,
+        k_batch_assemble<<<assemble_grid(G->rows_rt, G->nnz_rt), 256, 0, cs(P)>>>(d, nb, G->rows_rt, G->nnz_rt, vw,
                                                                           G->rt_rp.as<int64_t>(), G->rt_col.as<int32_t>(),
                                                                           G->rt_val.p);
     }));
     SPG_TRY(launch(P, "batch_assemble", [&] {
-        k_batch_assemble<<<grid_for(G->rows_a + 1, 256), 256, 0, cs(P)>>>(d + nb, nb, G->rows_a, G->nnz_a, vw,
+        k_batch_assemble<<<assemble_grid(G->rows_a, G->nnz_a), 256, 0, cs(P)>>>(d + nb, nb, G->rows_a, G->nnz_a, vw,
                                                                          G->a_rp.as<int64_t>(), G->a_col.as<int32_t>(),
                                                                          G->a_val.p);
     }));
     SPG_TRY(launch(P, "batch_assemble", [&] {
-        k_batch_assemble<<<grid_for(G->rows_r + 1, 256), 256, 0, cs(P)>>>(d + 2 * nb, nb, G->rows_r, G->nnz_r, vw,
+        k_batch_assemble<<<assemble_grid(G->rows_r, G->nnz_r), 256, 0, cs(P)>>>(d + 2 * nb, nb, G->rows_r, G->nnz_r, vw,
                                                                          G->r_rp.as<int64_t>(), G->r_col.as<int32_t>(),
                                                                          G->r_val.p);
     }));

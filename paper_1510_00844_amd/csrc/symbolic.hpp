@@ -22,19 +22,40 @@ constexpr int MAX_CHUNKS = 128;  // column chunks per row recorded by the bitmap
 // is walked in order, so flat order is ascending k, then ascending column.
 __device__ inline bool wave_locate_product(const Csr& A, const Csr& B, int64_t beg, int64_t end,
                                            int64_t& p_out, int64_t& q_out) {
+    // Lane f takes the f-th product of the row in (A entry, B entry) order.
+    // Up to 64 A entries at a time: each lane loads one entry's B segment,
+    // a wave scan gives the segment offsets, and each lane finds the segment
+    // holding its product by a binary search over the scanned offsets.
     const int lane = lane_id();
-    int pos = 0;
+    int pos = 0;  // products in earlier groups of A entries
     bool have = false;
-    for (int64_t p = beg; p < end && pos < SPG_WAVE; ++p) {
-        int64_t k = A.col[p];
-        int64_t bs = B.rp[k];
-        int len = (int)(B.rp[k + 1] - bs);
-        if (lane >= pos && lane < pos + len) {
-            p_out = p;
-            q_out = bs + (lane - pos);
+    for (int64_t base = beg; base < end && pos < SPG_WAVE; base += SPG_WAVE) {
+        const int64_t p = base + lane;
+        int64_t bs = 0;
+        int len = 0;
+        if (p < end) {
+            const int64_t k = A.col[p];
+            bs = B.rp[k];
+            len = (int)(B.rp[k + 1] - bs);
+        }
+        const int incl = wave_inclusive_scan_add(len);
+        const int total = __shfl(incl, SPG_WAVE - 1, SPG_WAVE);
+        const int f = lane - pos;
+        int t = 0;  // first lane whose inclusive count exceeds f
+#pragma unroll
+        for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
+            const int v = __shfl(incl, t + step - 1, SPG_WAVE);
+            if (v <= f) t += step;
+        }
+        t = t < SPG_WAVE ? t : SPG_WAVE - 1;
+        const int64_t bst = __shfl(bs, t, SPG_WAVE);
+        const int excl = __shfl(incl - len, t, SPG_WAVE);
+        if (f >= 0 && f < total) {
+            p_out = base + t;
+            q_out = bst + (f - excl);
             have = true;
         }
-        pos += len;
+        pos += total;
     }
     return have;
 }
