@@ -258,6 +258,22 @@ spg_status spgemm_galerkin_batched(spg_plan plan, spg_semiring sr, int32_t nb, c
  * batched call on the plan. */
 spg_status spgemm_galerkin_copy(spg_plan plan, int64_t* row_ptr, int32_t* col, void* val);
 
+/* Autotuner of the batched Galerkin products: picks the bin thresholds,
+ * gather mappings and stream count (fields small_max_flops, streams,
+ * gather_map, unroll, sym_gather_map, hash_max_nnz of spg_opts) that
+ * minimize the graph-replay time of spgemm_galerkin_batched on these
+ * instances, by coordinate descent from the plan's options, each candidate
+ * timed with HIP events over 5 replays, within about budget_ms of wall time
+ * (<= 0: no limit).  Results are cached in the text file cache_path (one
+ * JSON object per line, keyed by GPU architecture, CU count, semiring and
+ * the instances' sizes; NULL = no cache): a cached key is used without
+ * timing and *from_cache is set to 1.  The plan adopts the chosen options
+ * (its batched state is reset); *best (may be NULL) receives them.
+ * Synchronizes; allocates and frees temporary plans. */
+spg_status spg_autotune_galerkin(spg_plan plan, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                                 const spg_csr* A, const spg_csr* R, const char* cache_path,
+                                 int32_t budget_ms, spg_opts* best, int32_t* from_cache);
+
 const char* spg_status_string(spg_status s);
 const char* spg_last_error(void);
 

@@ -106,6 +106,8 @@ def lib():
             "spgemm_learned_fetch": ([P, CP, CP, P, P, P], ctypes.c_int),
             "spgemm_galerkin_batched": ([P, ctypes.c_int, I32, CP, CP, CP, CP, I32], ctypes.c_int),
             "spgemm_galerkin_copy": ([P, P, P, P], ctypes.c_int),
+            "spg_autotune_galerkin": ([P, ctypes.c_int, I32, CP, CP, CP, ctypes.c_char_p, I32, ctypes.POINTER(Opts),
+                                       ctypes.POINTER(I32)], ctypes.c_int),
             "spg_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "spg_last_error": ([], ctypes.c_char_p),
         }
@@ -379,3 +381,22 @@ def spgemm_galerkin_batched(plan: Plan, sr: str, RT: Sequence[DeviceCSR], A: Seq
     out = (_Csr * nb)()
     _check(lib().spgemm_galerkin_batched(plan.handle, SEMIRINGS[sr], nb, rt, a, r, out, int(bool(use_graph))))
     return GalerkinBatch(out, sr)
+
+
+TUNED_FIELDS = ("small_max_flops", "streams", "gather_map", "unroll", "sym_gather_map", "hash_max_nnz")
+
+
+def spg_autotune_galerkin(plan: Plan, sr: str, RT: Sequence[DeviceCSR], A: Sequence[DeviceCSR],
+                          R: Sequence[DeviceCSR], cache_path: Optional[str] = None, budget_ms: int = 5000):
+    """Tune the plan's options for these batched Galerkin instances (or take
+    them from the JSON-lines cache); returns (chosen options, from_cache)."""
+    nb = len(A)
+    rt = (_Csr * nb)(*[m._c(sr) for m in RT])
+    a = (_Csr * nb)(*[m._c(sr) for m in A])
+    r = (_Csr * nb)(*[m._c(sr) for m in R])
+    best = Opts()
+    hit = ctypes.c_int32()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().spg_autotune_galerkin(plan.handle, SEMIRINGS[sr], nb, rt, a, r, path, int(budget_ms),
+                                       ctypes.byref(best), ctypes.byref(hit)))
+    return {k: int(getattr(best, k)) for k in TUNED_FIELDS}, bool(hit.value)

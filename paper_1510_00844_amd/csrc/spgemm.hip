@@ -1727,3 +1727,190 @@ void spg_release_galerkin(spg_plan P) {
     galerkin_free(it->second);
     m.erase(it);
 }
+
+// ---------------------------------------------------------------------------
+// autotuner of the batched Galerkin products
+// ---------------------------------------------------------------------------
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+
+namespace {
+
+// knobs the tuner varies, with their candidate values
+struct TuneKnob {
+    const char* name;
+    int32_t spg_opts::*field;
+    std::vector<int32_t> values;
+};
+
+std::vector<TuneKnob> tune_knobs() {
+    return {
+        {"small_max_flops", &spg_opts::small_max_flops, {16, 32, 64}},
+        {"streams", &spg_opts::streams, {1, 2, 4}},
+        {"gather_map", &spg_opts::gather_map, {1, 2}},
+        {"unroll", &spg_opts::unroll, {4, 8}},
+        {"sym_gather_map", &spg_opts::sym_gather_map, {1, 2}},
+        {"hash_max_nnz", &spg_opts::hash_max_nnz, {2048, 4096}},
+    };
+}
+
+// device and workload key of a cache entry: architecture, CU count, the
+// semiring and every instance's sizes (folded into a 64-bit FNV-1a hash)
+std::string tune_key(int device, spg_semiring sr, int32_t nb, const spg_csr* RT, const spg_csr* A,
+                     const spg_csr* R) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (char& ch : arch)
+        if (ch == '"' || ch == ' ' || ch == ':') ch = '_';
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    int64_t tot = 0;
+    for (int b = 0; b < nb; ++b) {
+        for (const spg_csr* M : {&RT[b], &A[b], &R[b]}) {
+            mix(M->nrows);
+            mix(M->ncols);
+            mix(M->nnz);
+            tot += M->nnz;
+        }
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "galerkin:%s:cu%d:sr%d:nb%d:nnz%lld:%016llx", arch.c_str(), cus, (int)sr, (int)nb,
+                  (long long)tot, (unsigned long long)h);
+    return buf;
+}
+
+// one JSON object per line: {"key": "...", "ms": t, "opts": {"name": v, ...}}
+bool tune_cache_lookup(const char* path, const std::string& key, spg_opts* o) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line, want = "\"key\": \"" + key + "\"";
+    bool found = false;
+    while (std::getline(f, line)) {
+        if (line.find(want) == std::string::npos) continue;
+        spg_opts t = *o;
+        bool ok = true;
+        for (const TuneKnob& k : tune_knobs()) {
+            const std::string field = "\"" + std::string(k.name) + "\": ";
+            size_t p = line.find(field);
+            if (p == std::string::npos) {
+                ok = false;
+                break;
+            }
+            t.*(k.field) = (int32_t)std::strtol(line.c_str() + p + field.size(), nullptr, 10);
+        }
+        if (ok) {
+            *o = t;  // the last matching line wins
+            found = true;
+        }
+    }
+    return found;
+}
+
+bool tune_cache_store(const char* path, const std::string& key, const spg_opts& o, double ms) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return false;
+    std::fprintf(f, "{\"key\": \"%s\", \"ms\": %.4f, \"opts\": {", key.c_str(), ms);
+    bool first = true;
+    for (const TuneKnob& k : tune_knobs()) {
+        std::fprintf(f, "%s\"%s\": %d", first ? "" : ", ", k.name, (int)(o.*(k.field)));
+        first = false;
+    }
+    std::fprintf(f, "}}\n");
+    return std::fclose(f) == 0;
+}
+
+}  // namespace
+
+// Time one candidate: a fresh plan on the caller's stream, one eager call
+// (which captures the graph), one warm replay, then `reps` replays between
+// two events.
+static spg_status tune_time(spg_plan P, const spg_opts& o, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                            const spg_csr* A, const spg_csr* R, spg_csr* out, int reps, float* ms) {
+    spg_plan T = nullptr;
+    SPG_TRY(spg_plan_create(&T, (void*)P->stream, &o));
+    spg_status st = spgemm_galerkin_batched(T, sr, nb, RT, A, R, out, 1);
+    if (st == SPG_OK) st = spgemm_galerkin_batched(T, sr, nb, RT, A, R, out, 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == SPG_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(SPG_ERR_HIP, "hipEventCreate failed");
+    if (st == SPG_OK) {
+        hipEventRecord(e0, P->stream);
+        for (int r = 0; r < reps && st == SPG_OK; ++r) st = spgemm_galerkin_batched(T, sr, nb, RT, A, R, out, 1);
+        hipEventRecord(e1, P->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) st = fail(SPG_ERR_HIP, "timing event failed");
+        float t = 0.f;
+        if (st == SPG_OK) {
+            hipEventElapsedTime(&t, e0, e1);
+            *ms = t / (float)reps;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    spg_plan_destroy(T);
+    return st;
+}
+
+extern "C" spg_status spg_autotune_galerkin(spg_plan P, spg_semiring sr, int32_t nb, const spg_csr* RT,
+                                            const spg_csr* A, const spg_csr* R, const char* cache_path,
+                                            int32_t budget_ms, spg_opts* best, int32_t* from_cache) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    if (nb < 1 || !RT || !A || !R) return fail(SPG_ERR_ARG, "need nb >= 1 and non-NULL arrays");
+    if (from_cache) *from_cache = 0;
+    const std::string key = tune_key(P->device, sr, nb, RT, A, R);
+    spg_opts cur = P->opts;
+    cur.profile = 0;
+    if (cache_path && tune_cache_lookup(cache_path, key, &cur)) {
+        if (from_cache) *from_cache = 1;
+    } else {
+        std::vector<spg_csr> out((size_t)nb);
+        const auto t_start = std::chrono::steady_clock::now();
+        auto elapsed_ms = [&] {
+            return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        };
+        float best_ms = 0.f;
+        SPG_TRY(tune_time(P, cur, sr, nb, RT, A, R, out.data(), 5, &best_ms));
+        // coordinate descent: each knob over its candidates, the others
+        // held at the best so far; two sweeps or until the budget is spent
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            bool improved = false;
+            for (const TuneKnob& k : tune_knobs()) {
+                for (int32_t v : k.values) {
+                    if (budget_ms > 0 && elapsed_ms() > budget_ms) break;
+                    if (cur.*(k.field) == v) continue;
+                    spg_opts cand = cur;
+                    cand.*(k.field) = v;
+                    if (cand.chunk_min_nnz > cand.hash_max_nnz) cand.chunk_min_nnz = cand.hash_max_nnz;
+                    float t = 0.f;
+                    SPG_TRY(tune_time(P, cand, sr, nb, RT, A, R, out.data(), 5, &t));
+                    if (t < 0.98f * best_ms) {  // a clear gain only
+                        best_ms = t;
+                        cur = cand;
+                        improved = true;
+                    }
+                }
+            }
+            if (!improved) break;
+        }
+        if (cache_path && !tune_cache_store(cache_path, key, cur, best_ms))
+            return fail(SPG_ERR_ARG, std::string("cannot append to the tuning cache ") + cache_path);
+    }
+    // the plan takes the chosen options; its batched state starts afresh
+    const int32_t prof = P->opts.profile, val = P->opts.validate;
+    spg_release_galerkin(P);
+    P->opts = cur;
+    P->opts.profile = prof;
+    P->opts.validate = val;
+    if (best) *best = cur;
+    return SPG_OK;
+}

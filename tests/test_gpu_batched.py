@@ -179,3 +179,31 @@ def test_batched_errors(plan):
         spg.spgemm_galerkin_batched(plan, "f64", [dR], [dA], [dR])  # R in place of RT: shapes
     with pytest.raises(ValueError):
         spg.spgemm_galerkin_batched(plan, "f64", [dRT, dRT], [dA], [dR])
+
+
+def test_autotune_cache(tmp_path):
+    """The tuner returns valid options, the tuned plan gives the same
+    result, and a second call reads the cache instead of timing."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    inst = _small_batch()
+    cache = str(tmp_path / "tune.jsonl")
+    p = spg.Plan()
+    try:
+        dev = [(to_dev(RT), to_dev(A), to_dev(R)) for RT, A, R in inst]
+        args = ([d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev])
+        ref = [to_host(C) for C in spg.spgemm_galerkin_batched(p, "f64", *args).fetch(p)]
+        opts, hit = spg.spg_autotune_galerkin(p, "f64", *args, cache_path=cache, budget_ms=3000)
+        assert not hit
+        assert opts["streams"] in (1, 2, 4) and opts["gather_map"] in (1, 2) and opts["unroll"] in (4, 8)
+        assert 0 < opts["small_max_flops"] <= 64 and 0 < opts["hash_max_nnz"] <= 4096
+        got = [to_host(C) for C in spg.spgemm_galerkin_batched(p, "f64", *args).fetch(p)]
+        for x, y in zip(got, ref):
+            assert_same_structure(x, y)
+            assert np.array_equal(x.val, y.val)
+        opts2, hit2 = spg.spg_autotune_galerkin(p, "f64", *args, cache_path=cache, budget_ms=3000)
+        assert hit2 and opts2 == opts
+        lines = open(cache).read().strip().splitlines()
+        assert len(lines) == 1 and '"key": "galerkin:' in lines[0]
+    finally:
+        p.close()
