@@ -93,7 +93,9 @@ typedef struct {
     int32_t rank_max_nnz;      /* numeric rows with a saved bitmap and at most this many outputs
                                   accumulate the whole row in one workgroup (capacities 4096, 8192,
                                   16384 as the LDS allows; below 4096: never) */
-    int32_t reserved[2];
+    int32_t rank_block;        /* threads per workgroup of the whole-row rank accumulator: 512 or 1024
+                                  (1024: more loads in flight, capacities up to 8192) */
+    int32_t reserved[1];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;

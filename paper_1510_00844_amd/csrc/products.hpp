@@ -9,6 +9,7 @@
 // LDS finds its first segment, after which it walks forward.  No thread walks
 // a long B row alone and no product pays for a search.
 #pragma once
+#include <cstdint>
 #include "common.hpp"
 
 namespace spg {
@@ -186,19 +187,34 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                     const int32_t flast = (fs + SPG_WAVE - 1 < f1 ? fs + SPG_WAVE - 1 : f1 - 1);
                     int t = ta;
                     if (fs < f1 && flast >= L.off[ta + 1]) {
-                        // a segment boundary falls inside the step
-                        int hi = NT;
-                        while (hi - t > 1) {
-                            int mid = (t + hi) >> 1;
-                            if (L.off[mid] <= f) t = mid; else hi = mid;
+                        // Segment boundaries inside the step (ta is the last
+                        // segment starting at or before fs).  Lane j holds the
+                        // start of segment ta+j relative to fs; each lane finds
+                        // the last of those 64 starts at or before its product
+                        // by a binary search over the lanes (shuffles).
+                        const int j = ta + lane;
+                        const int32_t dj = (j <= NT ? L.off[j] : INT32_MAX) - fs;
+                        const int32_t me = f - fs;
+                        int lo = 0;
+#pragma unroll
+                        for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
+                            const int32_t v = __shfl(dj, lo + step, SPG_WAVE);
+                            if (v <= me) lo += step;
                         }
-                        // next step starts in the segment of this step's last product
-                        int tl = ta, h2 = NT;
-                        while (h2 - tl > 1) {
-                            int mid = (tl + h2) >> 1;
-                            if (L.off[mid] <= flast) tl = mid; else h2 = mid;
+                        t = ta + lo;
+                        // more than 64 segments start in the step (empty B
+                        // rows): the lanes past the 64th search all segments
+                        const int32_t o64 = ta + SPG_WAVE <= NT ? L.off[ta + SPG_WAVE] : INT32_MAX;
+                        if (o64 <= flast && f >= o64) {
+                            int hi = NT;
+                            t = ta + SPG_WAVE;
+                            while (hi - t > 1) {
+                                int mid = (t + hi) >> 1;
+                                if (L.off[mid] <= f) t = mid; else hi = mid;
+                            }
                         }
-                        ta = tl;
+                        // the next step starts after this step's last product
+                        ta = __shfl(t, SPG_WAVE - 1, SPG_WAVE);
                     }
                     tt[u] = t;
                     qq[u] = L.bstart[t] + (f - L.off[t]);

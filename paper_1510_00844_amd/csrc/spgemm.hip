@@ -208,6 +208,8 @@ static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per
 
 // static LDS of k_num_rank<*, 512> (A values, product offsets, scan scratch), with margin
 static const int RANK_STATIC_LDS = (int)(8 * 512 + sizeof(ProductLds<512>) + 4 * 16 + 256);
+static const int RANK_STATIC_LDS_1024 = (int)(8 * 1024 + sizeof(ProductLds<1024>) + 4 * 32 + 256);
+static int rank_static_lds(spg_plan P) { return P->opts.rank_block == 1024 ? RANK_STATIC_LDS_1024 : RANK_STATIC_LDS; }
 // rank-chunk items: at most this many outputs and this many column chunks
 static const int RANKC_CAP = 4096;
 
@@ -226,12 +228,13 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->streams = 4;
     o->gather_map = 1;
     o->unroll = 4;
-    o->sym_gather_map = 2;
-    o->sym_unroll = 8;
+    o->sym_gather_map = 1;
+    o->sym_unroll = 4;
     o->dense_chunk_cols = 4096;
     o->chunk_min_nnz = 4096;
-    o->chunk_group = 128;
-    o->rank_max_nnz = 16384;
+    o->chunk_group = 32;
+    o->rank_max_nnz = 8192;
+    o->rank_block = 512;
 }
 
 extern "C" const char* spg_status_string(spg_status s) {
@@ -259,6 +262,10 @@ static void set_lds_attributes(spg_plan P) {
     hipFuncSetAttribute((const void*)k_num_rank<SR_F64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
     hipFuncSetAttribute((const void*)k_num_rank<SR_I64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
     hipFuncSetAttribute((const void*)k_num_rank<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    const int dyn_rank_1024 = std::max(0, P->max_lds - RANK_STATIC_LDS_1024);
+    hipFuncSetAttribute((const void*)k_num_rank<SR_F64, 1024, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank_1024);
+    hipFuncSetAttribute((const void*)k_num_rank<SR_I64, 1024, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank_1024);
+    hipFuncSetAttribute((const void*)k_num_rank<SR_BOOL, 1024, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank_1024);
     hipFuncSetAttribute((const void*)k_num_rankc<SR_F64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
     hipFuncSetAttribute((const void*)k_num_rankc<SR_I64, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
     hipFuncSetAttribute((const void*)k_num_rankc<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
@@ -304,6 +311,7 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         if (!P->opts.chunk_min_nnz) P->opts.chunk_min_nnz = P->opts.hash_max_nnz;
         if (!P->opts.chunk_group) P->opts.chunk_group = d.chunk_group;
         if (!P->opts.rank_max_nnz) P->opts.rank_max_nnz = d.rank_max_nnz;
+        if (!P->opts.rank_block) P->opts.rank_block = d.rank_block;
     }
     auto map_ok = [](int m) { return m == 1 || m == 2; };
     auto unroll_ok = [](int u) { return u == 4 || u == 8; };
@@ -323,6 +331,10 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 4096) {
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
+    }
+    if (P->opts.rank_block != 512 && P->opts.rank_block != 1024) {
+        delete P;
+        return fail(SPG_ERR_ARG, "rank_block must be 512 or 1024");
     }
     if (P->opts.chunk_min_nnz < 1 || P->opts.chunk_min_nnz > P->opts.hash_max_nnz || P->opts.chunk_group < 1 ||
         P->opts.chunk_group > MAX_CHUNKS) {
@@ -526,7 +538,7 @@ static BinParams bin_params(spg_plan P, int64_t n) {
     if (bp.dense_ok) {
         const int64_t words = 2 * bitmap_bytes;
         for (int lg = 14; lg >= RANK_MIN_LOG2; --lg)
-            if ((1ll << lg) <= P->opts.rank_max_nnz && words + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) {
+            if ((1ll << lg) <= P->opts.rank_max_nnz && words + (8ll << lg) + rank_static_lds(P) <= P->max_lds) {
                 bp.rank_max_log2 = lg;
                 break;
             }
@@ -772,9 +784,14 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             const size_t lds = (size_t)nwords * 8 + (size_t)cap * sizeof(typename Sr<SR>::acc_t);
             SPG_TRY(with_gm(P, [&](auto gm) {
                 return launch(P, "num_rank" + std::to_string(cap), [&] {
-                    k_num_rank<SR, 512, decltype(gm)::value><<<(unsigned)nr, 512, lds, cs(P)>>>(
-                        a, b, rows, ab, ae, P->bm_save.as<uint32_t>(), P->heavy_idx.as<int32_t>(), nwords, crp, ccol,
-                        cval);
+                    if (P->opts.rank_block == 1024)
+                        k_num_rank<SR, 1024, decltype(gm)::value><<<(unsigned)nr, 1024, lds, cs(P)>>>(
+                            a, b, rows, ab, ae, P->bm_save.as<uint32_t>(), P->heavy_idx.as<int32_t>(), nwords, crp,
+                            ccol, cval);
+                    else
+                        k_num_rank<SR, 512, decltype(gm)::value><<<(unsigned)nr, 512, lds, cs(P)>>>(
+                            a, b, rows, ab, ae, P->bm_save.as<uint32_t>(), P->heavy_idx.as<int32_t>(), nwords, crp,
+                            ccol, cval);
                 });
             }));
         } else if (bb == BIN_DENSE_PAR) {
@@ -782,7 +799,11 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             // an item holds at least one whole chunk (<= W outputs); group as
             // many chunks as the LDS allows, up to RANKC_GROUP
             const int32_t RC = std::max(RANKC_CAP, W);
-            int32_t G = std::min<int32_t>(chunks, P->opts.chunk_group);
+            // chunks per item: about RC outputs at the bin's mean density,
+            // at most chunk_group
+            const double per_chunk = (double)P->num_counts[3 * NBINS + bb] / ((double)nr * chunks);
+            int32_t G = (int32_t)std::lround(per_chunk > 0 ? RC / per_chunk : (double)chunks);
+            G = std::max(1, std::min({G, chunks, P->opts.chunk_group}));
             while (G > 1 && (int64_t)G * (W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) --G;
             SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(nr * chunks, 1), "rank items"));
             SPG_TRY(P->small_i32.ensure(64 * 4, "counters"));

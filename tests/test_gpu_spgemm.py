@@ -187,14 +187,22 @@ def test_all_products_in_one_column(plan):
         check_full_vs_oracle(run(plan, sr, AA, BB), AA, BB, sr)
 
 
-@pytest.mark.parametrize("ncols,want", [(9000, 15), (20000, 11), (262144, 14), (1 << 20, 12)])
-def test_dense_operands(plan, ncols, want):
+@pytest.mark.parametrize("ncols,want,opts", [
+    (9000, 15, dict(rank_max_nnz=16384)), (9000, 11, {}), (6000, 14, dict(rank_block=1024)),
+    (9000, 15, dict(rank_block=1024, rank_max_nnz=16384)), (20000, 11, {}), (20000, 11, dict(chunk_group=1)),
+    (262144, 14, {}), (1 << 20, 12, {})])
+def test_dense_operands(ncols, want, opts):
     """Large output rows.  Dense operands with 9000 columns fit the
-    rank-space accumulator (bin rank16384); with 20000 outputs per row they
-    take rank chunks of the saved bitmap (dense_par); with 262144 columns
-    and 20 entries per B row, rank8192; with 2^20 columns one LDS bitmap no
-    longer covers a row, so the bitmap pass counts in column blocks and the
-    numeric pass sweeps column chunks in one workgroup (dense)."""
+    rank-space accumulator of 16384 outputs when it is enabled (rank16384),
+    else take rank chunks of the saved bitmap (dense_par); with 1024-thread
+    rank workgroups 6000 outputs take rank8192; with 20000 outputs per row
+    rank chunks, also one chunk per item; with 262144 columns and 20 entries
+    per B row, rank8192; with 2^20 columns one LDS bitmap no longer covers a
+    row, so the bitmap pass counts in column blocks and the numeric pass
+    sweeps column chunks in one workgroup (dense)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    plan = spg.Plan(**opts)
     A = synth.random_csr(40, 300, 1.0, 5, "f64")
     if ncols < 100000:
         B = synth.random_csr(300, ncols, 1.0, 6, "f64")
@@ -205,6 +213,7 @@ def test_dense_operands(plan, ncols, want):
         B = synth.canonical_from_coo(300, ncols, rr, cc, rng.random(rr.size), dup="first")
     C = run(plan, "f64", A, B)
     st = plan.stats()
+    plan.close()
     assert st["num_rows"][want] == 40, st["num_rows"]
     check_full_vs_oracle(C, A, B, "f64")
 
