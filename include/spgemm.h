@@ -94,7 +94,8 @@ typedef struct {
                                   accumulate the whole row in one workgroup (capacities 4096, 8192,
                                   16384 as the LDS allows; below 4096: never) */
     int32_t rank_block;        /* threads per workgroup of the whole-row rank accumulator: 512 or 1024
-                                  (1024: more loads in flight, capacities up to 8192) */
+                                  (1024: more loads in flight; capacity 16384 only when the LDS
+                                  allows it) */
     int32_t reserved[1];
 } spg_opts;
 

@@ -369,6 +369,25 @@ __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* r
     }
 }
 
+// Copy nw bitmap words from global memory into the low halves of the LDS
+// words bw[] with coalesced loads, the first 8 per thread issued together.
+template <int NT>
+__device__ inline void stage_bitmap_words(const uint32_t* src, int nw, uint64_t* bw) {
+    constexpr int K = 8;
+    uint32_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int w = threadIdx.x + k * NT;
+        v[k] = w < nw ? src[w] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int w = threadIdx.x + k * NT;
+        if (w < nw) bw[w] = v[k];
+    }
+    for (int w = threadIdx.x + K * NT; w < nw; w += NT) bw[w] = src[w];
+}
+
 // Dynamic LDS: nwords 64-bit words (bits in the low half, count of set bits
 // in all earlier words in the high half), then `cap` accumulators.
 template <int SR, int NT, int GM>
@@ -389,16 +408,18 @@ __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* ro
     const int64_t off = c_rp[i];
     const int32_t cnt = (int32_t)(c_rp[i + 1] - off);
     const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords;
+    stage_bitmap_words<NT>(src, nwords, bw);
+    __syncthreads();
     // each thread owns a contiguous run of words
     const int wpt = (nwords + NT - 1) / NT;
     const int w0 = threadIdx.x * wpt;
     const int w1 = w0 + wpt < nwords ? w0 + wpt : nwords;
     int32_t part = 0;
-    for (int w = w0; w < w1; ++w) part += __popc(src[w]);
+    for (int w = w0; w < w1; ++w) part += __popc((uint32_t)bw[w]);
     int32_t dummy;
     int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
     for (int w = w0; w < w1; ++w) {
-        uint32_t bits = src[w];
+        uint32_t bits = (uint32_t)bw[w];
         bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
         while (bits) {
             const int b = __ffs(bits) - 1;
@@ -493,15 +514,17 @@ __global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const
         const int64_t off = c_rp[i] + item.roff;
         const int32_t cbase = item.c0 * W;
         // packed words and columns, one contiguous run of words per thread
+        stage_bitmap_words<NT>(src, nw, bw);
+        __syncthreads();
         const int wpt = (nw + NT - 1) / NT;
         const int w0 = threadIdx.x * wpt;
         const int w1 = w0 + wpt < nw ? w0 + wpt : nw;
         int32_t part = 0;
-        for (int w = w0; w < w1; ++w) part += __popc(src[w]);
+        for (int w = w0; w < w1; ++w) part += __popc((uint32_t)bw[w]);
         int32_t dummy;
         int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
         for (int w = w0; w < w1; ++w) {
-            uint32_t bits = src[w];
+            uint32_t bits = (uint32_t)bw[w];
             bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
             while (bits) {
                 const int b = __ffs(bits) - 1;

@@ -147,7 +147,9 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
     }
     constexpr int NW = NT / SPG_WAVE;
     const int lane = lane_id();
-    const int wid = threadIdx.x / SPG_WAVE;
+    // wave-uniform values live in scalar registers (readfirstlane), so the
+    // step bookkeeping below is scalar work and scalar branches
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SPG_WAVE));
     for (int64_t base = a_beg; base < a_end; base += NT) {
         const int64_t p = base + threadIdx.x;
         int64_t bs = 0;
@@ -162,17 +164,18 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
         L.bstart[threadIdx.x] = bs;
         if (threadIdx.x == 0) L.off[NT] = total;
         __syncthreads();
-        const int32_t span = (total + NW - 1) / NW;
+        const int32_t tot = __builtin_amdgcn_readfirstlane(total);
+        const int32_t span = (tot + NW - 1) / NW;
         const int32_t f0 = wid * span;
-        const int32_t f1 = f0 + span < total ? f0 + span : total;
+        const int32_t f1 = f0 + span < tot ? f0 + span : tot;
         if (f0 < f1) {
-            // segment of the range start (same for every lane: broadcast reads)
+            // segment of the range start
             int ta = 0;
             {
                 int hi = NT;
                 while (hi - ta > 1) {
                     int mid = (ta + hi) >> 1;
-                    if (L.off[mid] <= f0) ta = mid; else hi = mid;
+                    if (__builtin_amdgcn_readfirstlane(L.off[mid]) <= f0) ta = mid; else hi = mid;
                 }
             }
             for (int32_t fb = f0; fb < f1; fb += SPG_WAVE * U) {
@@ -186,7 +189,7 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                     ok[u] = f < f1;
                     const int32_t flast = (fs + SPG_WAVE - 1 < f1 ? fs + SPG_WAVE - 1 : f1 - 1);
                     int t = ta;
-                    if (fs < f1 && flast >= L.off[ta + 1]) {
+                    if (fs < f1 && flast >= __builtin_amdgcn_readfirstlane(L.off[ta + 1])) {
                         // Segment boundaries inside the step (ta is the last
                         // segment starting at or before fs).  Lane j holds the
                         // start of segment ta+j relative to fs; each lane finds
@@ -204,7 +207,8 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                         t = ta + lo;
                         // more than 64 segments start in the step (empty B
                         // rows): the lanes past the 64th search all segments
-                        const int32_t o64 = ta + SPG_WAVE <= NT ? L.off[ta + SPG_WAVE] : INT32_MAX;
+                        const int32_t o64 =
+                            ta + SPG_WAVE <= NT ? __builtin_amdgcn_readfirstlane(L.off[ta + SPG_WAVE]) : INT32_MAX;
                         if (o64 <= flast && f >= o64) {
                             int hi = NT;
                             t = ta + SPG_WAVE;
@@ -214,7 +218,7 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                             }
                         }
                         // the next step starts after this step's last product
-                        ta = __shfl(t, SPG_WAVE - 1, SPG_WAVE);
+                        ta = __builtin_amdgcn_readlane(t, SPG_WAVE - 1);
                     }
                     tt[u] = t;
                     qq[u] = L.bstart[t] + (f - L.off[t]);

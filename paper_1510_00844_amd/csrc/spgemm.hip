@@ -234,7 +234,7 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->chunk_min_nnz = 4096;
     o->chunk_group = 32;
     o->rank_max_nnz = 8192;
-    o->rank_block = 512;
+    o->rank_block = 1024;
 }
 
 extern "C" const char* spg_status_string(spg_status s) {
