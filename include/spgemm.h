@@ -77,7 +77,7 @@ typedef struct {
     int32_t small_max_flops;   /* rows with at most this many products use one wave (<= 64) */
     int32_t hash_max_flops;    /* symbolic: LDS hash table up to this many products per row */
     int32_t hash_max_nnz;      /* numeric: LDS hash table up to this many outputs per row */
-    int32_t dense_chunk_cols;  /* numeric dense rows: columns per LDS chunk (power of two) */
+    int32_t dense_chunk_cols;  /* numeric dense rows: columns per LDS chunk (2048, 4096, 8192 or 16384) */
     int32_t profile;           /* 1: time every kernel launch with HIP events */
     int32_t streams;           /* streams independent bins are spread over (1..4) */
     int32_t gather_map;        /* numeric heavy rows, products per lane: 1 = neighbouring lanes take

@@ -341,9 +341,10 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         delete P;
         return fail(SPG_ERR_ARG, "chunk_min_nnz must be in [1, hash_max_nnz], chunk_group in [1, 128]");
     }
-    if (P->opts.dense_chunk_cols != 16384 && P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096) {
+    if (P->opts.dense_chunk_cols != 16384 && P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096 &&
+        P->opts.dense_chunk_cols != 2048) {
         delete P;
-        return fail(SPG_ERR_ARG, "dense_chunk_cols must be 4096, 8192 or 16384");
+        return fail(SPG_ERR_ARG, "dense_chunk_cols must be 2048, 4096, 8192 or 16384");
     }
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
@@ -798,7 +799,8 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             // an item holds at least one whole chunk (<= W outputs); group as
             // many chunks as the LDS allows, up to RANKC_GROUP
-            const int32_t RC = std::max(RANKC_CAP, W);
+            // outputs per item: at least one whole chunk (<= W outputs)
+            const int32_t RC = W < RANKC_CAP ? W : std::max(RANKC_CAP, W);
             // chunks per item: about RC outputs at the bin's mean density,
             // at most chunk_group
             const double per_chunk = (double)P->num_counts[3 * NBINS + bb] / ((double)nr * chunks);
@@ -865,12 +867,16 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                     else
                         k_num_dense<SR, 512, 8192, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
-            } else {
+            } else if (W == 4096) {
                 SPG_TRY(launch(P, name, [&] {
                     if (par)
                         k_num_dense<SR, 512, 4096, true, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                     else
                         k_num_dense<SR, 512, 4096, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                }));
+            } else {
+                SPG_TRY(launch(P, name, [&] {
+                    k_num_dense<SR, 512, 2048, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
                 }));
             }
                 return SPG_OK;

@@ -15,7 +15,7 @@
 namespace spg {
 
 constexpr int32_t EMPTY_KEY = -1;
-constexpr int MAX_CHUNKS = 128;  // column chunks per row recorded by the bitmap pass
+constexpr int MAX_CHUNKS = 256;  // column chunks per row recorded by the bitmap pass
 
 // Locate, for each lane, the product with flat index = lane among the row's
 // products (<= 64 of them): returns the A index p and B index q.  The A row

@@ -277,7 +277,7 @@ def test_errors(plan):
     vplan.close()
 
 
-@pytest.mark.parametrize("cols", [4096, 8192, 16384])
+@pytest.mark.parametrize("cols", [2048, 4096, 8192, 16384])
 def test_rmat_s19_c5_chunk_widths(cols):
     """C5 shape with every dense chunk width: with 4096 columns a row has
     128 chunks and the (row, chunk) work items exceed what one grid can hold,
