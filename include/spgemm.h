@@ -96,7 +96,9 @@ typedef struct {
     int32_t rank_block;        /* threads per workgroup of the whole-row rank accumulator: 512 or 1024
                                   (1024: more loads in flight; capacity 16384 only when the LDS
                                   allows it) */
-    int32_t reserved[1];
+    int32_t serial_heavy;      /* the this-many bins with the most work run back to back on the plan's
+                                  stream; the other bins are spread over the streams (0..16) */
+    int32_t reserved[4];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;
@@ -173,6 +175,9 @@ typedef struct {
 } spg_kernel_time;
 spg_status spg_profile_read(spg_plan plan, spg_kernel_time* out, int32_t cap, int32_t* n);
 spg_status spg_profile_reset(spg_plan plan);
+/* Time only the launches named `name` (the names spg_profile_read reports;
+ * NULL or "" = every launch), so the other launches run without events. */
+spg_status spg_profile_select(spg_plan plan, const char* name);
 
 /* ------------------------------------------------------------------------
  * Row-size predictor (not in the paper; its Section 3 notes that computing

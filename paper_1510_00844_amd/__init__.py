@@ -47,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("sym_gather_map", ctypes.c_int32), ("sym_unroll", ctypes.c_int32),
                 ("chunk_min_nnz", ctypes.c_int32), ("chunk_group", ctypes.c_int32),
                 ("rank_max_nnz", ctypes.c_int32), ("rank_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("serial_heavy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -97,6 +97,7 @@ def lib():
             "spg_plan_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
             "spg_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], ctypes.c_int),
             "spg_profile_reset": ([P], ctypes.c_int),
+            "spg_profile_select": ([P, ctypes.c_char_p], ctypes.c_int),
             "spg_mlp_forward": ([P, P, P, I64, P], ctypes.c_int),
             "spg_mlp_grad": ([P, P, P, P, I64, ctypes.c_float, P, P], ctypes.c_int),
             "spg_mlp_adam": ([P, P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
@@ -168,7 +169,7 @@ class Plan:
     def __init__(self, device=None, stream: Optional[torch.cuda.Stream] = None, validate=False,
                  profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
                  dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0,
-                 chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0, rank_block=0):
+                 chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0, rank_block=0, serial_heavy=-1):
         L = lib()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
@@ -185,6 +186,8 @@ class Plan:
                             ("rank_max_nnz", rank_max_nnz), ("rank_block", rank_block)):
                 if v:
                     setattr(o, name, int(v))
+            if serial_heavy >= 0:
+                o.serial_heavy = int(serial_heavy)
             h = ctypes.c_void_p()
             _check(L.spg_plan_create(ctypes.byref(h), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(o)))
         self.handle = h
@@ -216,6 +219,10 @@ class Plan:
 
     def profile_reset(self):
         _check(lib().spg_profile_reset(self.handle))
+
+    def profile_select(self, name: Optional[str] = None):
+        """Time only launches of this name (None: all)."""
+        _check(lib().spg_profile_select(self.handle, None if name is None else name.encode()))
 
 
 def _window(A: DeviceCSR, k_lo, k_hi):

@@ -256,19 +256,35 @@ __global__ void __launch_bounds__(256) k_copy_rows(int64_t nrows, const int32_t*
                                                    const int64_t* src_off, const int64_t* dst_rp,
                                                    const int32_t* src_col, const void* src_val, int32_t* dst_col,
                                                    void* dst_val) {
-    typedef Sr<SR> S;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= nrows) return;
-    const int64_t i = list ? list[r] : r;
-    if (!list && redo[i]) return;
-    const int64_t s = list ? src_off[r] : src_off[i];
-    const int64_t d = dst_rp[i];
-    const int64_t len = dst_rp[i + 1] - d;
-    for (int64_t x = lane_id(); x < len; x += SPG_WAVE) {
-        dst_col[d + x] = src_col[s + x];
-        if (dst_val) {
-            if (SR == SR_BOOL) ((uint8_t*)dst_val)[d + x] = ((const uint8_t*)src_val)[s + x];
-            else ((uint64_t*)dst_val)[d + x] = ((const uint64_t*)src_val)[s + x];
+    // one workgroup per row (grid-stride), four entries in flight per thread
+    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int64_t i = list ? list[r] : r;
+        if (!list && redo[i]) continue;
+        const int64_t s = list ? src_off[r] : src_off[i];
+        const int64_t d = dst_rp[i];
+        const int64_t len = dst_rp[i + 1] - d;
+        for (int64_t x0 = 0; x0 < len; x0 += 4 * 256) {
+            int32_t c[4];
+            uint64_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t x = x0 + u * 256 + threadIdx.x;
+                if (x < len) {
+                    c[u] = src_col[s + x];
+                    if (dst_val) v[u] = SR == SR_BOOL ? ((const uint8_t*)src_val)[s + x] : ((const uint64_t*)src_val)[s + x];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t x = x0 + u * 256 + threadIdx.x;
+                if (x < len) {
+                    dst_col[d + x] = c[u];
+                    if (dst_val) {
+                        if (SR == SR_BOOL) ((uint8_t*)dst_val)[d + x] = (uint8_t)v[u];
+                        else ((uint64_t*)dst_val)[d + x] = v[u];
+                    }
+                }
+            }
         }
     }
 }

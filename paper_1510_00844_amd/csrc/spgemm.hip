@@ -134,6 +134,7 @@ struct spg_plan_s {
 
     // profiling
     std::vector<ProfRec> prof_pending;
+    std::string prof_only;  // non-empty: time only launches of this name
     std::vector<hipEvent_t> event_pool;
     std::vector<spg_kernel_time> prof_acc;
 };
@@ -158,7 +159,8 @@ template <class F>
 static spg_status launch(spg_plan P, const std::string& name, F&& f) {
     hipEvent_t b = nullptr, e = nullptr;
     hipStream_t st = P->cur ? P->cur : P->stream;
-    if (P->opts.profile) {
+    const bool timed = P->opts.profile && (P->prof_only.empty() || P->prof_only == name);
+    if (timed) {
         b = take_event(P);
         e = take_event(P);
         hipEventRecord(b, st);
@@ -166,7 +168,7 @@ static spg_status launch(spg_plan P, const std::string& name, F&& f) {
     f();
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(SPG_ERR_HIP, std::string("launch ") + name + ": " + hipGetErrorString(err));
-    if (P->opts.profile) {
+    if (timed) {
         hipEventRecord(e, st);
         P->prof_pending.push_back({name, b, e});
     }
@@ -189,8 +191,16 @@ static spg_status join_streams(spg_plan P) {
     P->cur = nullptr;
     return SPG_OK;
 }
+// Stream of the bin at position `slot` of the work order: the first
+// serial_heavy bins run back to back on the plan's stream, the others
+// round-robin over the streams.
 static void use_stream(spg_plan P, int slot) {
-    slot %= P->opts.streams;
+    const int h = P->opts.serial_heavy;
+    if (slot < h) {
+        P->cur = P->stream;
+        return;
+    }
+    slot = (h > 0 ? slot - h + 1 : slot) % P->opts.streams;
     P->cur = slot == 0 ? P->stream : P->aux[slot - 1];
 }
 
@@ -331,6 +341,10 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 4096) {
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
+    }
+    if (P->opts.serial_heavy < 0 || P->opts.serial_heavy > NBINS) {
+        delete P;
+        return fail(SPG_ERR_ARG, "serial_heavy must be in [0, 16]");
     }
     if (P->opts.rank_block != 512 && P->opts.rank_block != 1024) {
         delete P;
@@ -1118,6 +1132,12 @@ extern "C" spg_status spg_profile_read(spg_plan P, spg_kernel_time* out, int32_t
     return SPG_OK;
 }
 
+extern "C" spg_status spg_profile_select(spg_plan P, const char* name) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->prof_only = name ? name : "";
+    return SPG_OK;
+}
+
 extern "C" spg_status spg_profile_reset(spg_plan P) {
     if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
     HIP_TRY(hipStreamSynchronize(P->stream));
@@ -1419,7 +1439,7 @@ static spg_status learned_fetch_sr(spg_plan P, const spg_csr* A, const spg_csr* 
     const int64_t m = P->lsig.m;
     if (m > 0) {
         SPG_TRY(launch(P, "copy_rows", [&] {
-            k_copy_rows<SR><<<grid_for(m, 4), 256, 0, cs(P)>>>(m, nullptr, P->fb_redo.as<uint8_t>(), P->slot.as<int64_t>(),
+            k_copy_rows<SR><<<(unsigned)std::min<int64_t>(m, 65536), 256, 0, cs(P)>>>(m, nullptr, P->fb_redo.as<uint8_t>(), P->slot.as<int64_t>(),
                                                                 c_row_ptr, P->pcol.as<int32_t>(), P->pval.p, c_col, c_val);
         }));
     }
@@ -1432,7 +1452,7 @@ static spg_status learned_fetch_sr(spg_plan P, const spg_csr* A, const spg_csr* 
                                P->sub_ccol.as<int32_t>(), c_val ? P->sub_cval.p : nullptr));
         P->cur = nullptr;
         SPG_TRY(launch(P, "copy_rows", [&] {
-            k_copy_rows<SR><<<grid_for(P->l_nfb, 4), 256, 0, cs(P)>>>(P->l_nfb, P->fb_list.as<int32_t>(), nullptr,
+            k_copy_rows<SR><<<(unsigned)std::min<int64_t>(P->l_nfb, 65536), 256, 0, cs(P)>>>(P->l_nfb, P->fb_list.as<int32_t>(), nullptr,
                                                                        P->sub_crp.as<int64_t>(), c_row_ptr,
                                                                        P->sub_ccol.as<int32_t>(), P->sub_cval.p, c_col,
                                                                        c_val);
