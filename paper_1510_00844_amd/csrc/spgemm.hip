@@ -191,17 +191,20 @@ static spg_status join_streams(spg_plan P) {
     P->cur = nullptr;
     return SPG_OK;
 }
-// Stream of the bin at position `slot` of the work order: the first
-// serial_heavy bins run back to back on the plan's stream, the others
-// round-robin over the streams.
-static void use_stream(spg_plan P, int slot) {
-    const int h = P->opts.serial_heavy;
-    if (slot < h) {
-        P->cur = P->stream;
-        return;
-    }
-    slot = (h > 0 ? slot - h + 1 : slot) % P->opts.streams;
-    P->cur = slot == 0 ? P->stream : P->aux[slot - 1];
+// Bins go to streams longest-processing-time first: each bin (in order of
+// decreasing work) to the stream with the least work so far; the first
+// serial_heavy bins stay on the plan's stream.  Work = products + 32 per row.
+struct StreamLoad {
+    double load[NAUX + 1] = {};
+};
+static void use_stream(spg_plan P, StreamLoad& L, int pos, const int64_t* counts, int bin) {
+    const double work = (double)counts[NBINS + bin] + 32.0 * (double)counts[bin];
+    int s = 0;
+    if (pos >= P->opts.serial_heavy)
+        for (int k = 1; k < P->opts.streams; ++k)
+            if (L.load[k] < L.load[s]) s = k;
+    L.load[s] += work;
+    P->cur = s == 0 ? P->stream : P->aux[s - 1];
 }
 
 // Order of the non-empty bins by work, largest first, so the heaviest
@@ -645,12 +648,13 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->sym_counts[x];
     SPG_TRY(fork_streams(P));
     const std::vector<int> sym_order = bins_by_work(P->sym_counts, P->sym_counts + NBINS);
+    StreamLoad sload;
     for (size_t oi = 0; oi < sym_order.size(); ++oi) {
         const int bb = sym_order[oi];
         const int64_t nr = P->sym_counts[bb];
         const int32_t* rows = lists + bin_off[bb];
         if (nr == 0 || bb == BIN_EMPTY || bb == BIN_TINY) continue;
-        use_stream(P, (int)oi);
+        use_stream(P, sload, (int)oi, P->sym_counts, bb);
         if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "sym_small", [&] {
                 k_sym_small<<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
@@ -779,12 +783,13 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
     }
     SPG_TRY(fork_streams(P));
     const std::vector<int> num_order = bins_by_work(P->num_counts, P->num_counts + NBINS);
+    StreamLoad nload;
     for (size_t oi = 0; oi < num_order.size(); ++oi) {
         const int bb = num_order[oi];
         const int64_t nr = P->num_counts[bb];
         const int32_t* rows = lists + bin_off[bb];
         if (nr == 0 || bb == BIN_EMPTY) continue;
-        use_stream(P, (int)oi);
+        use_stream(P, nload, (int)oi, P->num_counts, bb);
         if (bb == BIN_TINY) {
             SPG_TRY(launch(P, "num_tiny", [&] {
                 k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, crp, ccol, cval);
@@ -1227,12 +1232,13 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->l_counts[x];
     SPG_TRY(fork_streams(P));
     const std::vector<int> order = bins_by_work(P->l_counts, P->l_counts + NBINS);
+    StreamLoad lload;
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const int bb = order[oi];
         const int64_t nr = P->l_counts[bb];
         const int32_t* rows = lists + bin_off[bb];
         if (nr == 0 || bb == BIN_EMPTY || bb == BIN_DENSE) continue;
-        use_stream(P, (int)oi);
+        use_stream(P, lload, (int)oi, P->l_counts, bb);
         if (bb == BIN_TINY) {
             SPG_TRY(launch(P, "num_tiny", [&] {
                 k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, slot, pcol, pval);
