@@ -45,19 +45,39 @@ __device__ inline int find_instance_nz(const BatchDesc* d, int32_t nb, int64_t e
 // Grid-stride over x < max(rows + 1, nnz): row pointer x (shifted by the
 // entries before its instance) and entry x (column shifted by the columns
 // before its instance, value copied), so reads and writes are coalesced.
+// The instances' first rows and entries are staged in LDS for the searches.
 // vw = value bytes (8 or 1; 0 = no values).
+constexpr int BATCH_LDS_MAX = 1024;  // instances whose offsets fit the LDS tables
+
+__device__ inline int find_sorted(const int64_t* off, int32_t nb, int64_t x) {
+    int lo = 0, hi = nb;  // largest b with off[b] <= x
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(256) k_batch_assemble(const BatchDesc* d, int32_t nb, int64_t rows, int64_t nnz,
                                                         int32_t vw, int64_t* rp, int32_t* col, void* val) {
+    __shared__ int64_t s_row[BATCH_LDS_MAX], s_nz[BATCH_LDS_MAX];
+    const bool lds = nb <= BATCH_LDS_MAX;
+    if (lds)
+        for (int b = threadIdx.x; b < nb; b += 256) {
+            s_row[b] = d[b].row_off;
+            s_nz[b] = d[b].nz_off;
+        }
+    __syncthreads();
     const int64_t n = rows + 1 > nnz ? rows + 1 : nnz;
     for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256) {
         if (x < rows) {
-            const BatchDesc& D = d[find_instance(d, nb, x)];
+            const BatchDesc& D = d[lds ? find_sorted(s_row, nb, x) : find_instance(d, nb, x)];
             rp[x] = D.nz_off + (D.rp[x - D.row_off] - D.rp[0]);
         } else if (x == rows) {
             rp[rows] = nnz;
         }
         if (x < nnz) {
-            const BatchDesc& D = d[find_instance_nz(d, nb, x)];
+            const BatchDesc& D = d[lds ? find_sorted(s_nz, nb, x) : find_instance_nz(d, nb, x)];
             const int64_t e = x - D.nz_off + D.rp[0];
             col[x] = (int32_t)(D.col[e] + D.col_off);
             if (vw == 8) ((uint64_t*)val)[x] = ((const uint64_t*)D.val)[e];
