@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (3 times), the reference for "
                          "scaling the HBM byte counters")
+    ap.add_argument("--no-isolated", action="store_true",
+                    help="skip the second pass that times every kernel alone (roofline_isolated)")
     ap.add_argument("--tune-cache", default=None, help="JSON-lines cache of the batched autotuner")
     ap.add_argument("--tune-budget-ms", type=int, default=3000)
     ap.add_argument("--mode", default="c2", choices=["c2", "c3", "c4", "c5"],
@@ -396,10 +398,16 @@ def main():
     torch.cuda.synchronize()
     dom = None
     if not args.no_profile:
-        # the dominant kernel by time over the warmup steps (every launch
-        # timed); the timed steps then carry events around its launches only
+        # the dominant kernel: the one that moves the most algorithmic bytes
+        # per step (over the warmup steps, every launch timed); the timed
+        # steps then carry events around its launches only
         prof0 = plan.profile_read()
-        cands = {k: v[1] for k, v in prof0.items() if k not in ("fill", "scan")}
+        st0 = plan.stats()
+        cands = {}
+        for k, (launches, _) in prof0.items():
+            b = kernel_bytes(k, st0, sr)
+            if b == b:  # kernels with a byte model (product kernels)
+                cands[k] = b * launches
         dom = max(cands, key=cands.get) if cands else None
         plan.profile_select(dom)
         plan.profile_reset()
@@ -426,7 +434,8 @@ def main():
         byts = kernel_bytes(dom, st, sr)
         ach = byts / (avg_ms * 1e-3) / 1e9
         tr = measured_traffic(dom)
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+        roofline = {"bound": "hbm", "kernel": dom, "dominant_by": "algorithmic bytes per step",
+                    "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": None if tr is None else tr["total_bytes"],
                     "bytes_per_launch": byts, "avg_launch_ms": round(avg_ms, 5)}
@@ -434,7 +443,7 @@ def main():
             roofline["traffic_detail"] = tr
     # context: every kernel alone (one stream), so each launch has the GPU to itself
     roofline_isolated = None
-    if not args.no_profile:
+    if not args.no_profile and not args.no_isolated:
         piso = spg.Plan(profile=True, streams=1)
         for _ in range(2):
             rp_i, n_i = spg.spgemm_symbolic(piso, sr, dA, dA)
@@ -449,8 +458,8 @@ def main():
         iso_ms = (time.perf_counter() - t0) * 1e3 / 3
         pi = piso.profile_read()
         sti = piso.stats()
-        cand = {k: v for k, v in pi.items() if k not in ("fill", "scan")}
-        kd = max(cand, key=lambda k: cand[k][1])
+        cand = {k: v for k, v in pi.items() if kernel_bytes(k, sti, sr) == kernel_bytes(k, sti, sr)}
+        kd = max(cand, key=lambda k: kernel_bytes(k, sti, sr) * cand[k][0])
         launches, total = cand[kd]
         byts_i = kernel_bytes(kd, sti, sr)
         avg_i = total / launches
