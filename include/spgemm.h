@@ -282,6 +282,35 @@ spg_status spg_autotune_galerkin(spg_plan plan, spg_semiring sr, int32_t nb, con
                                  const spg_csr* A, const spg_csr* R, const char* cache_path,
                                  int32_t budget_ms, spg_opts* best, int32_t* from_cache);
 
+/* ------------------------------------------------------------------------
+ * Restriction operators from distance-2 maximal independent sets (Section
+ * 5.3, Algorithm 3).  A: a square device CSR whose pattern is an undirected
+ * graph (symmetric pattern; values ignored).  In rounds until no candidate
+ * is left, every candidate vertex draws a 64-bit key (SplitMix64 output of
+ * seed ^ (round << 32 | vertex) in the high half, the vertex in the low
+ * half); the candidates holding the smallest key within distance two join
+ * the set, and they and every candidate within distance two of them stop
+ * being candidates (two (min, select2nd) matrix-vector products per step).
+ * Aggregates: each set vertex roots one, numbered in vertex order, with its
+ * distance-1 neighbours; every other vertex joins the assigned neighbour
+ * with the smallest SplitMix64 choice key.
+ * in_mis: device, n bytes (1 = in the set); agg: device, n int32 aggregate
+ * numbers; *n_agg (host): number of aggregates; *rounds (host, may be
+ * NULL): rounds taken.  Synchronizes every round.  SPG_ERR_SHAPE if A is
+ * not square; SPG_ERR_STATE if the rounds do not end (asymmetric pattern).
+ * ------------------------------------------------------------------------ */
+spg_status spg_mis2_aggregate(spg_plan plan, const spg_csr* A, uint64_t seed, uint8_t* in_mis, int32_t* agg,
+                              int64_t* n_agg, int32_t* rounds);
+
+/* R (n x n_agg) with R(i, agg[i]) = one, and R^T (n_agg x n), as canonical
+ * CSR in caller-owned device arrays: r_rp n+1, r_col n, r_val n; rt_rp
+ * n_agg+1, rt_col n, rt_val n (values typed by the semiring: 1.0, 1 or
+ * true; r_val/rt_val may be NULL).  Synchronizes.  SPG_ERR_CAPACITY if an
+ * aggregate holds more than 4096 vertices. */
+spg_status spg_restriction(spg_plan plan, spg_semiring sr, int64_t n, int64_t n_agg, const int32_t* agg,
+                           int64_t* r_rp, int32_t* r_col, void* r_val, int64_t* rt_rp, int32_t* rt_col,
+                           void* rt_val);
+
 const char* spg_status_string(spg_status s);
 const char* spg_last_error(void);
 

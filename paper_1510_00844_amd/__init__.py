@@ -110,6 +110,9 @@ def lib():
             "spgemm_galerkin_copy": ([P, P, P, P], ctypes.c_int),
             "spg_autotune_galerkin": ([P, ctypes.c_int, I32, CP, CP, CP, ctypes.c_char_p, I32, ctypes.POINTER(Opts),
                                        ctypes.POINTER(I32)], ctypes.c_int),
+            "spg_mis2_aggregate": ([P, CP, ctypes.c_uint64, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
+                                   ctypes.c_int),
+            "spg_restriction": ([P, ctypes.c_int, I64, I64, P, P, P, P, P, P, P], ctypes.c_int),
             "spg_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "spg_last_error": ([], ctypes.c_char_p),
         }
@@ -408,3 +411,34 @@ def spg_autotune_galerkin(plan: Plan, sr: str, RT: Sequence[DeviceCSR], A: Seque
     _check(lib().spg_autotune_galerkin(plan.handle, SEMIRINGS[sr], nb, rt, a, r, path, int(budget_ms),
                                        ctypes.byref(best), ctypes.byref(hit)))
     return {k: int(getattr(best, k)) for k in TUNED_FIELDS}, bool(hit.value)
+
+
+def spg_mis2_aggregate(plan: Plan, A: DeviceCSR, seed: int):
+    """Distance-2 maximal independent set and aggregates of A's graph;
+    returns (in_mis uint8 tensor, agg int32 tensor, n_agg, rounds)."""
+    n = A.nrows
+    in_mis = torch.empty(max(n, 1), dtype=torch.uint8, device=plan.device)
+    agg = torch.empty(max(n, 1), dtype=torch.int32, device=plan.device)
+    na = ctypes.c_int64()
+    rounds = ctypes.c_int32()
+    a = A._c(None)
+    _check(lib().spg_mis2_aggregate(plan.handle, ctypes.byref(a), ctypes.c_uint64(seed & ((1 << 64) - 1)),
+                                    _vp(in_mis), _vp(agg), ctypes.byref(na), ctypes.byref(rounds)))
+    return in_mis[:n], agg[:n], na.value, rounds.value
+
+
+def spg_restriction(plan: Plan, sr: str, agg: torch.Tensor, n_agg: int):
+    """(R, R^T) as DeviceCSR from the aggregate of every vertex."""
+    n = agg.numel()
+    dt = TORCH_DTYPE[sr]
+    r_rp = torch.empty(n + 1, dtype=torch.int64, device=plan.device)
+    r_col = torch.empty(max(n, 1), dtype=torch.int32, device=plan.device)
+    r_val = torch.empty(max(n, 1), dtype=dt, device=plan.device)
+    rt_rp = torch.empty(n_agg + 1, dtype=torch.int64, device=plan.device)
+    rt_col = torch.empty(max(n, 1), dtype=torch.int32, device=plan.device)
+    rt_val = torch.empty(max(n, 1), dtype=dt, device=plan.device)
+    _check(lib().spg_restriction(plan.handle, SEMIRINGS[sr], n, n_agg, _vp(agg), _vp(r_rp), _vp(r_col), _vp(r_val),
+                                 _vp(rt_rp), _vp(rt_col), _vp(rt_val)))
+    R = DeviceCSR(n, n_agg, r_rp, r_col[:n], r_val[:n])
+    RT = DeviceCSR(n_agg, n, rt_rp, rt_col[:n], rt_val[:n])
+    return R, RT

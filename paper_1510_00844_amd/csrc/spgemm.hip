@@ -14,6 +14,7 @@
 #include "../../include/spgemm.h"
 #include "batched.hpp"
 #include "learned.hpp"
+#include "mis2.hpp"
 #include "merge.hpp"
 #include "numeric.hpp"
 #include "rowinfo.hpp"
@@ -126,6 +127,9 @@ struct spg_plan_s {
     int64_t l_counts[2 * NBINS];
     int64_t l_nfb = 0, l_nexact = 0, l_slots = 0, l_nnz = 0, l_sub_nnz = 0, l_sub_annz = 0;
     spg_semiring l_sr = SPG_SR_PLUS_TIMES_F64;
+
+    // distance-2 independent sets and aggregation
+    DevBuf mis_key, mis_m1, mis_cand, mis_new, mis_a1, mis_flags, mis_agg1, mis_ctr;
 
     // merge state
     std::vector<LayerDesc> merge_sig;
@@ -409,7 +413,9 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
                       &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
                       &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save, &P->rank_items,
                       &P->lcap, &P->lcnt, &P->slot, &P->pcol, &P->pval, &P->fb_list, &P->fb_redo, &P->sub_rp,
-                      &P->sub_col, &P->sub_val, &P->sub_crp, &P->sub_ccol, &P->sub_cval, &P->mlp_tmp})
+                      &P->sub_col, &P->sub_val, &P->sub_crp, &P->sub_ccol, &P->sub_cval, &P->mlp_tmp,
+                      &P->mis_key, &P->mis_m1, &P->mis_cand, &P->mis_new, &P->mis_a1, &P->mis_flags, &P->mis_agg1,
+                      &P->mis_ctr})
         b->release();
     if (P->sub) spg_plan_destroy(P->sub);
     if (P->h_stats) hipHostFree(P->h_stats);
@@ -476,6 +482,10 @@ __global__ void __launch_bounds__(256) k_validate(Csr M, int32_t* bad) {
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_bytes(uint8_t* p, int64_t n, uint8_t v) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
 }
@@ -1966,4 +1976,128 @@ extern "C" spg_status spg_autotune_galerkin(spg_plan P, spg_semiring sr, int32_t
     P->opts.validate = val;
     if (best) *best = cur;
     return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// distance-2 maximal independent set, aggregation, restriction operator
+// ---------------------------------------------------------------------------
+static const int32_t MIS_MAX_ROUNDS = 4096;
+
+static unsigned grid_rows(int64_t n) { return grid_for(n * MIS_LANES, 256); }
+
+extern "C" spg_status spg_mis2_aggregate(spg_plan P, const spg_csr* A, uint64_t seed, uint8_t* in_mis, int32_t* agg,
+                                         int64_t* n_agg, int32_t* rounds) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->cur = nullptr;
+    SPG_TRY(check_csr(A, "A", SPG_SR_OR_AND_BOOL, false));
+    if (A->nrows != A->ncols) return fail(SPG_ERR_SHAPE, "A must be square (a graph)");
+    if (!in_mis || !agg || !n_agg) return fail(SPG_ERR_ARG, "in_mis, agg and n_agg must not be NULL");
+    const int64_t n = A->nrows;
+    if (rounds) *rounds = 0;
+    *n_agg = 0;
+    if (n == 0) return SPG_OK;
+    if (P->opts.validate) SPG_TRY(validate_csr(P, A, "A"));
+    SPG_TRY(P->mis_key.ensure(8 * (size_t)n, "MIS-2 keys"));
+    SPG_TRY(P->mis_m1.ensure(8 * (size_t)n, "MIS-2 minima"));
+    SPG_TRY(P->mis_cand.ensure((size_t)n, "MIS-2 candidates"));
+    SPG_TRY(P->mis_new.ensure((size_t)n, "MIS-2 new vertices"));
+    SPG_TRY(P->mis_a1.ensure((size_t)n, "MIS-2 neighbourhood"));
+    SPG_TRY(P->mis_flags.ensure(8 * (size_t)(n + 1), "MIS-2 root numbers"));
+    SPG_TRY(P->mis_agg1.ensure(4 * (size_t)n, "aggregates"));
+    SPG_TRY(P->mis_ctr.ensure(64, "counters"));
+    Csr a = view(A);
+    uint8_t* cand = P->mis_cand.as<uint8_t>();
+    uint8_t* news = P->mis_new.as<uint8_t>();
+    uint8_t* a1 = P->mis_a1.as<uint8_t>();
+    uint64_t* key = P->mis_key.as<uint64_t>();
+    uint64_t* m1 = P->mis_m1.as<uint64_t>();
+    int32_t* ctr = P->mis_ctr.as<int32_t>();
+    // fill kernels, not memsets (the sequence may be captured)
+    auto fill_u8 = [&](uint8_t* p, uint8_t v) -> spg_status {
+        return launch(P, "fill", [&] { k_fill_bytes<<<grid_for(n, 256), 256, 0, cs(P)>>>(p, n, v); });
+    };
+    SPG_TRY(fill_u8(cand, 1));
+    SPG_TRY(fill_u8(in_mis, 0));
+    int32_t r = 0;
+    for (;; ++r) {
+        if (r >= MIS_MAX_ROUNDS) return fail(SPG_ERR_STATE, "MIS-2 did not finish (pattern not symmetric?)");
+        SPG_TRY(fill_i32(P, ctr, 1, 0));
+        SPG_TRY(launch(P, "mis_keys", [&] {
+            k_mis_keys<<<grid_for(n, 256), 256, 0, cs(P)>>>(n, cand, seed, r, key);
+        }));
+        SPG_TRY(launch(P, "mis_row_min", [&] { k_mis_row_min<<<grid_rows(n), 256, 0, cs(P)>>>(a, key, m1); }));
+        SPG_TRY(launch(P, "mis_select", [&] { k_mis_select<<<grid_rows(n), 256, 0, cs(P)>>>(a, key, m1, cand, news); }));
+        SPG_TRY(launch(P, "mis_row_any", [&] { k_mis_row_any<<<grid_rows(n), 256, 0, cs(P)>>>(a, news, a1); }));
+        SPG_TRY(launch(P, "mis_prune", [&] {
+            k_mis_prune<<<grid_rows(n), 256, 0, cs(P)>>>(a, a1, news, cand, in_mis, ctr);
+        }));
+        int32_t left = 0;
+        HIP_TRY(hipMemcpyAsync(&left, ctr, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        if (left == 0) break;
+    }
+    if (rounds) *rounds = r + 1;
+    // aggregates: roots numbered in vertex order, then their neighbours, then the rest
+    int64_t* flags = P->mis_flags.as<int64_t>();
+    SPG_TRY(launch(P, "mis_flags", [&] { k_mis_flags<<<grid_for(n, 256), 256, 0, cs(P)>>>(n, in_mis, flags); }));
+    SPG_TRY(scan_counts(P, flags, n));
+    int32_t* agg1 = P->mis_agg1.as<int32_t>();
+    SPG_TRY(launch(P, "agg_roots", [&] { k_agg_roots<<<grid_rows(n), 256, 0, cs(P)>>>(a, in_mis, flags, agg1); }));
+    SPG_TRY(fill_i32(P, ctr + 1, 1, 0));
+    SPG_TRY(launch(P, "agg_rest", [&] { k_agg_rest<<<grid_rows(n), 256, 0, cs(P)>>>(a, agg1, seed, agg, ctr + 1); }));
+    int64_t h[2] = {0, 0};
+    int32_t un = 0;
+    HIP_TRY(hipMemcpyAsync(&h[0], flags + n, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipMemcpyAsync(&un, ctr + 1, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    if (un) return fail(SPG_ERR_STATE, "some vertices are farther than two hops from the independent set");
+    *n_agg = h[0];
+    return SPG_OK;
+}
+
+template <int SR>
+static spg_status restriction_sr(spg_plan P, int64_t n, int64_t na, const int32_t* agg, int64_t* r_rp, int32_t* r_col,
+                                 void* r_val, int64_t* rt_rp, int32_t* rt_col, void* rt_val) {
+    SPG_TRY(fill_i64(P, rt_rp, na + 1, 0));
+    if (n == 0) return fill_i64(P, r_rp, 1, 0);
+    SPG_TRY(launch(P, "restrict_rows", [&] {
+        k_restrict_rows<SR><<<grid_for(n + 1, 256), 256, 0, cs(P)>>>(n, agg, r_rp, r_col, r_val, rt_rp);
+    }));
+    SPG_TRY(scan_counts(P, rt_rp, na));
+    SPG_TRY(P->mis_flags.ensure(8 * (size_t)(na + 1), "restriction cursors"));
+    int64_t* cursor = P->mis_flags.as<int64_t>();
+    SPG_TRY(fill_i64(P, cursor, na, 0));
+    SPG_TRY(launch(P, "restrict_cols", [&] {
+        k_restrict_cols<SR><<<grid_for(n, 256), 256, 0, cs(P)>>>(n, agg, rt_rp, cursor, rt_col, rt_val);
+    }));
+    SPG_TRY(P->mis_ctr.ensure(64, "counters"));
+    int32_t* ctr = P->mis_ctr.as<int32_t>();
+    SPG_TRY(fill_i32(P, ctr + 2, 1, 0));
+    SPG_TRY(launch(P, "sort_row_cols", [&] {
+        k_sort_row_cols<<<(unsigned)na, 64, 0, cs(P)>>>(na, rt_rp, rt_col, ctr + 2);
+    }));
+    int32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    if (bad) return fail(SPG_ERR_CAPACITY, "an aggregate has more than 4096 vertices");
+    return SPG_OK;
+}
+
+extern "C" spg_status spg_restriction(spg_plan P, spg_semiring sr, int64_t n, int64_t n_agg, const int32_t* agg,
+                                      int64_t* r_rp, int32_t* r_col, void* r_val, int64_t* rt_rp, int32_t* rt_col,
+                                      void* rt_val) {
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    P->cur = nullptr;
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    if (n < 0 || n_agg < 0 || (n > 0 && n_agg < 1) || n >= (1ll << 31) || n_agg > n)
+        return fail(SPG_ERR_ARG, "need 0 <= n < 2^31 and 1 <= n_agg <= n");
+    if (!r_rp || !rt_rp || (n > 0 && (!agg || !r_col || !rt_col)))
+        return fail(SPG_ERR_ARG, "NULL output or aggregate array");
+    if (n > 0 && n_agg > (int64_t)UINT32_MAX) return fail(SPG_ERR_INDEX_RANGE, "too many aggregates");
+    switch (sr) {
+        case SPG_SR_PLUS_TIMES_F64: return restriction_sr<SR_F64>(P, n, n_agg, agg, r_rp, r_col, r_val, rt_rp, rt_col, rt_val);
+        case SPG_SR_PLUS_TIMES_I64: return restriction_sr<SR_I64>(P, n, n_agg, agg, r_rp, r_col, r_val, rt_rp, rt_col, rt_val);
+        case SPG_SR_OR_AND_BOOL: return restriction_sr<SR_BOOL>(P, n, n_agg, agg, r_rp, r_col, r_val, rt_rp, rt_col, rt_val);
+    }
+    return fail(SPG_ERR_ARG, "unknown semiring");
 }
