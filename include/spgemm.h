@@ -87,8 +87,8 @@ typedef struct {
     int32_t sym_unroll;
     int32_t chunk_min_nnz;     /* numeric rows whose bitmap was saved by the symbolic pass and that have
                                   more than this many outputs take column-chunk work items instead of
-                                  a hash table (1..hash_max_nnz) */
-    int32_t chunk_group;       /* most column chunks one such work item spans (1..128; the LDS may
+                                  a hash table (1..hash_max_nnz; 0 = hash_max_nnz) */
+    int32_t chunk_group;       /* most column chunks one such work item spans (1..256; the LDS may
                                   allow fewer) */
     int32_t rank_max_nnz;      /* numeric rows with a saved bitmap and at most this many outputs
                                   accumulate the whole row in one workgroup (capacities 4096, 8192,
@@ -98,7 +98,8 @@ typedef struct {
                                   allows it) */
     int32_t serial_heavy;      /* the this-many bins with the most work run back to back on the plan's
                                   stream; the other bins are spread over the streams (0..16) */
-    int32_t reserved[4];
+    int32_t chunk_unroll;      /* gathers in flight per lane in the rank-chunk items (4 or 8) */
+    int32_t reserved[3];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;

@@ -47,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("sym_gather_map", ctypes.c_int32), ("sym_unroll", ctypes.c_int32),
                 ("chunk_min_nnz", ctypes.c_int32), ("chunk_group", ctypes.c_int32),
                 ("rank_max_nnz", ctypes.c_int32), ("rank_block", ctypes.c_int32),
-                ("serial_heavy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("serial_heavy", ctypes.c_int32), ("chunk_unroll", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -172,7 +173,8 @@ class Plan:
     def __init__(self, device=None, stream: Optional[torch.cuda.Stream] = None, validate=False,
                  profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
                  dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0,
-                 chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0, rank_block=0, serial_heavy=-1):
+                 chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0, rank_block=0, serial_heavy=-1,
+                 chunk_unroll=0):
         L = lib()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
@@ -186,7 +188,8 @@ class Plan:
                             ("streams", streams), ("gather_map", gather_map), ("unroll", unroll),
                             ("sym_gather_map", sym_gather_map), ("sym_unroll", sym_unroll),
                             ("chunk_min_nnz", chunk_min_nnz), ("chunk_group", chunk_group),
-                            ("rank_max_nnz", rank_max_nnz), ("rank_block", rank_block)):
+                            ("rank_max_nnz", rank_max_nnz), ("rank_block", rank_block),
+                            ("chunk_unroll", chunk_unroll)):
                 if v:
                     setattr(o, name, int(v))
             if serial_heavy >= 0:

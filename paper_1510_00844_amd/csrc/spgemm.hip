@@ -248,10 +248,11 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->sym_gather_map = 1;
     o->sym_unroll = 4;
     o->dense_chunk_cols = 4096;
-    o->chunk_min_nnz = 4096;
+    o->chunk_min_nnz = 0;  // = hash_max_nnz
     o->chunk_group = 32;
     o->rank_max_nnz = 8192;
     o->rank_block = 1024;
+    o->chunk_unroll = 4;
 }
 
 extern "C" const char* spg_status_string(spg_status s) {
@@ -307,6 +308,16 @@ static spg_status with_gm(spg_plan P, F&& f, bool sym = false) {
     }
 }
 
+template <class F>
+static spg_status with_gm_u(spg_plan P, int map, int unroll, F&& f) {
+    switch (gather_mode(map, unroll)) {
+        case 0: return f(std::integral_constant<int, 0>());
+        case 1: return f(std::integral_constant<int, 1>());
+        case 2: return f(std::integral_constant<int, 2>());
+        default: return f(std::integral_constant<int, 3>());
+    }
+}
+
 extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opts* opts) {
     if (!out) return fail(SPG_ERR_ARG, "plan pointer is NULL");
     *out = nullptr;
@@ -329,7 +340,9 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         if (!P->opts.chunk_group) P->opts.chunk_group = d.chunk_group;
         if (!P->opts.rank_max_nnz) P->opts.rank_max_nnz = d.rank_max_nnz;
         if (!P->opts.rank_block) P->opts.rank_block = d.rank_block;
+        if (!P->opts.chunk_unroll) P->opts.chunk_unroll = d.chunk_unroll;
     }
+    if (!P->opts.chunk_min_nnz) P->opts.chunk_min_nnz = P->opts.hash_max_nnz;
     auto map_ok = [](int m) { return m == 1 || m == 2; };
     auto unroll_ok = [](int u) { return u == 4 || u == 8; };
     if (P->opts.streams < 1 || P->opts.streams > NAUX + 1 || !map_ok(P->opts.gather_map) ||
@@ -349,6 +362,10 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
     }
+    if (P->opts.chunk_unroll != 4 && P->opts.chunk_unroll != 8) {
+        delete P;
+        return fail(SPG_ERR_ARG, "chunk_unroll must be 4 or 8");
+    }
     if (P->opts.serial_heavy < 0 || P->opts.serial_heavy > NBINS) {
         delete P;
         return fail(SPG_ERR_ARG, "serial_heavy must be in [0, 16]");
@@ -360,7 +377,7 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     if (P->opts.chunk_min_nnz < 1 || P->opts.chunk_min_nnz > P->opts.hash_max_nnz || P->opts.chunk_group < 1 ||
         P->opts.chunk_group > MAX_CHUNKS) {
         delete P;
-        return fail(SPG_ERR_ARG, "chunk_min_nnz must be in [1, hash_max_nnz], chunk_group in [1, 128]");
+        return fail(SPG_ERR_ARG, "chunk_min_nnz must be in [1, hash_max_nnz], chunk_group in [1, 256]");
     }
     if (P->opts.dense_chunk_cols != 16384 && P->opts.dense_chunk_cols != 8192 && P->opts.dense_chunk_cols != 4096 &&
         P->opts.dense_chunk_cols != 2048) {
@@ -850,7 +867,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             const size_t lds = (size_t)G * (W / 32) * 8 + (size_t)RC * sizeof(typename Sr<SR>::acc_t);
             const int32_t* split = chunks > 1 ? P->split.as<int32_t>() : nullptr;
             const unsigned grid = (unsigned)std::min<int64_t>(nr * chunks, 256 * 8);
-            SPG_TRY(with_gm(P, [&](auto gm) {
+            SPG_TRY(with_gm_u(P, P->opts.gather_map, P->opts.chunk_unroll, [&](auto gm) {
                 return launch(P, "num_rankc", [&] {
                     k_num_rankc<SR, 512, decltype(gm)::value><<<grid, 512, lds, cs(P)>>>(
                         a, b, W, rows, ab, ae, P->bm_save.as<uint32_t>(), hi, nwords, split, chunks, items, nitems, RC, G,

@@ -307,3 +307,41 @@ def test_rmat_s19_c5_sampled(plan):
     check_rows_vs_oracle(C, A, A, "f64", rows)
     del C
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("opts", [
+    dict(hash_max_nnz=1024), dict(hash_max_nnz=512, chunk_min_nnz=256), dict(chunk_unroll=8),
+    dict(serial_heavy=2), dict(serial_heavy=16, streams=2), dict(streams=1, rank_block=512),
+    dict(rank_max_nnz=16384, rank_block=512), dict(rank_max_nnz=1, chunk_group=1),
+    dict(gather_map=2, unroll=8, sym_gather_map=2, sym_unroll=8), dict(small_max_flops=1, hash_max_flops=128)])
+def test_option_variants(opts):
+    """Every tuning option gives the oracle's product (R-MAT G500 scale 13,
+    FP64, plus an INT64 run for the exact values)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    A = synth.rmat(13, 16, synth.G500, seed=50)
+    p = spg.Plan(**opts)
+    try:
+        check_full_vs_oracle(run(p, "f64", A, A), A, A, "f64")
+        Ai = synth.with_values(A, "ones_i64")
+        check_full_vs_oracle(run(p, "i64", Ai, Ai), Ai, Ai, "i64")
+    finally:
+        p.close()
+
+
+def test_profile_select_times_one_kernel():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    A = synth.rmat(13, 16, synth.G500, seed=51)
+    p = spg.Plan(profile=True)
+    try:
+        run(p, "f64", A, A)
+        names = set(p.profile_read())
+        assert "rowinfo" in names and len(names) > 3
+        p.profile_reset()
+        p.profile_select("rowinfo")
+        run(p, "f64", A, A)
+        assert set(p.profile_read()) == {"rowinfo"}
+        p.profile_select(None)
+    finally:
+        p.close()
