@@ -282,6 +282,8 @@ def test_rmat_s19_c5_chunk_widths(cols):
     """C5 shape with every dense chunk width: with 4096 columns a row has
     128 chunks and the (row, chunk) work items exceed what one grid can hold,
     so the kernel must stride over them."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     A = synth.rmat(19, 16, synth.G500, seed=6)
     p = spg.Plan(dense_chunk_cols=cols)
     C = run(p, "f64", A, A)
