@@ -549,6 +549,17 @@ def main():
                         "ms": round(t1, 4), "flops": f1, "nnz_c": C1.nnz,
                         "gflops": round(2.0 * f1 / (t1 * 1e-3) / 1e9, 3)}
         p1.close()
+        # the SSCA class (.6, .4/3, .4/3, .4/3), edge factor 8, scale 16
+        As = synth.rmat(16, 8, synth.SSCA, seed=2)
+        ds = spg.DeviceCSR.from_arrays(As.nrows, As.ncols, As.row_ptr, As.col, As.val)
+        ps = spg.Plan()
+        ts_, Cs = _time(lambda: spg.spgemm(ps, "f64", ds, ds), 10)
+        fs_ = ps.stats()["flops"]
+        extras["ssca_s16"] = {"workload": "R-MAT SSCA (.6,.4/3,.4/3,.4/3) scale 16 edge factor 8, A*A FP64",
+                              "ms": round(ts_, 4), "flops": fs_, "nnz_c": Cs.nnz,
+                              "gflops": round(2.0 * fs_ / (ts_ * 1e-3) / 1e9, 3)}
+        ps.close()
+        del Cs
         extras.update(learned_modes(A, dA, args))
         extras["c4_batched"] = batched_modes(args)
         extras["c3_layers"] = layered_modes(args)

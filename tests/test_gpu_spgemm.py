@@ -347,3 +347,13 @@ def test_profile_select_times_one_kernel():
         p.profile_select(None)
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_ssca_class(plan, sr):
+    """The third synthetic class of the paper's experiments: R-MAT with the
+    SSCA parameters (.6, .4/3, .4/3, .4/3), edge factor 8, scale 15."""
+    A = synth.rmat(15, 8, synth.SSCA, seed=60)
+    if sr != "f64":
+        A = with_kind(A, sr)
+    check_full_vs_oracle(run(plan, sr, A, A), A, A, sr)
