@@ -115,6 +115,7 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     __shared__ int32_t red[NT / SPG_WAVE + 1];
     __shared__ int32_t mm[2 * (NT / SPG_WAVE)];
     __shared__ V s_av[NT];
+    __shared__ int32_t s_bucket[NT];
     const int64_t i = rows[blockIdx.x];
     for (int t = threadIdx.x; t < T; t += NT) {
         tkey[t] = EMPTY_KEY;
@@ -217,6 +218,59 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
             }
         }
         return;
+    }
+    // Wide spans: NT buckets of equal column width, one per thread.  The
+    // entries are counted per bucket, placed bucket by bucket, and each thread
+    // sorts its own bucket (insertion sort); then the row is written in order.
+    // Falls back to the full sort below when some bucket holds more than 32.
+    if (cnt <= T) {
+        const int64_t span = (int64_t)kmax - kmin + 1;
+        const int32_t width = (int32_t)((span + NT - 1) / NT);
+        s_bucket[threadIdx.x] = 0;
+        __syncthreads();
+        int32_t bl[PER];
+#pragma unroll
+        for (int s = 0; s < PER; ++s)
+            bl[s] = rk[s] != EMPTY_KEY ? atomicAdd(&s_bucket[(rk[s] - kmin) / width], 1) : 0;
+        __syncthreads();
+        const int32_t mycnt = s_bucket[threadIdx.x];
+        int32_t bmin = mycnt, bmax = mycnt;
+        block_min_max<NT, int32_t>(bmin, bmax, mm);
+        if (bmax <= 32) {
+            int32_t tot;
+            const int32_t boff = block_exclusive_scan<NT, int32_t>(mycnt, &tot, red);
+            s_bucket[threadIdx.x] = boff;
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < PER; ++s) {
+                if (rk[s] != EMPTY_KEY) {
+                    const int32_t q = s_bucket[(rk[s] - kmin) / width] + bl[s];
+                    tkey[q] = rk[s];
+                    tval[q] = rv[s];
+                }
+            }
+            __syncthreads();
+            for (int x = boff + 1; x < boff + mycnt; ++x) {
+                const int32_t kx = tkey[x];
+                const V vx = tval[x];
+                int y = x - 1;
+                while (y >= boff && tkey[y] > kx) {
+                    tkey[y + 1] = tkey[y];
+                    tval[y + 1] = tval[y];
+                    --y;
+                }
+                tkey[y + 1] = kx;
+                tval[y + 1] = vx;
+            }
+            __syncthreads();
+            const int32_t nout = cnt < cnt_sym ? cnt : cnt_sym;
+            for (int t = threadIdx.x; t < nout; t += NT) {
+                c_col[o + t] = tkey[t];
+                if (c_val) S::store(c_val, o + t, tval[t]);
+            }
+            return;
+        }
+        __syncthreads();
     }
     if (cnt > T / 2) cnt = T / 2;  // sort buffer capacity; only reached if inputs changed
     // reuse the table: compacted values in tkey's bytes, sort keys in tval's
