@@ -198,14 +198,29 @@ static spg_status join_streams(spg_plan P) {
 // Bins go to streams longest-processing-time first: each bin (in order of
 // decreasing work) to the stream with the least work so far; the first
 // serial_heavy bins stay on the plan's stream.  Work = products + 32 per row.
+// Streams in use: at most opts.streams, and no more than the number of bins
+// holding at least 5% of the work (more streams than heavy bins only splits
+// the GPU between a heavy kernel and small ones without shortening it).
+static double bin_work(const int64_t* counts, int bin) {
+    return (double)counts[NBINS + bin] + 32.0 * (double)counts[bin];
+}
 struct StreamLoad {
     double load[NAUX + 1] = {};
+    int nstreams = 1;
+    StreamLoad(spg_plan P, const int64_t* counts) {
+        double total = 0;
+        for (int b = 1; b < NBINS; ++b) total += bin_work(counts, b);
+        int heavy = 0;
+        for (int b = 1; b < NBINS; ++b)
+            if (counts[b] > 0 && bin_work(counts, b) >= 0.05 * total) ++heavy;
+        nstreams = std::max(1, std::min(P->opts.streams, heavy));
+    }
 };
 static void use_stream(spg_plan P, StreamLoad& L, int pos, const int64_t* counts, int bin) {
-    const double work = (double)counts[NBINS + bin] + 32.0 * (double)counts[bin];
+    const double work = bin_work(counts, bin);
     int s = 0;
     if (pos >= P->opts.serial_heavy)
-        for (int k = 1; k < P->opts.streams; ++k)
+        for (int k = 1; k < L.nstreams; ++k)
             if (L.load[k] < L.load[s]) s = k;
     L.load[s] += work;
     P->cur = s == 0 ? P->stream : P->aux[s - 1];
@@ -675,7 +690,7 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->sym_counts[x];
     SPG_TRY(fork_streams(P));
     const std::vector<int> sym_order = bins_by_work(P->sym_counts, P->sym_counts + NBINS);
-    StreamLoad sload;
+    StreamLoad sload(P, P->sym_counts);
     for (size_t oi = 0; oi < sym_order.size(); ++oi) {
         const int bb = sym_order[oi];
         const int64_t nr = P->sym_counts[bb];
@@ -810,7 +825,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
     }
     SPG_TRY(fork_streams(P));
     const std::vector<int> num_order = bins_by_work(P->num_counts, P->num_counts + NBINS);
-    StreamLoad nload;
+    StreamLoad nload(P, P->num_counts);
     for (size_t oi = 0; oi < num_order.size(); ++oi) {
         const int bb = num_order[oi];
         const int64_t nr = P->num_counts[bb];
@@ -1259,7 +1274,7 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->l_counts[x];
     SPG_TRY(fork_streams(P));
     const std::vector<int> order = bins_by_work(P->l_counts, P->l_counts + NBINS);
-    StreamLoad lload;
+    StreamLoad lload(P, P->l_counts);
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const int bb = order[oi];
         const int64_t nr = P->l_counts[bb];
