@@ -251,10 +251,12 @@ spg_status spgemm_learned_fetch(spg_plan plan, const spg_csr* A, const spg_csr* 
  * instances.  The first call with a given set of descriptors runs eagerly
  * (and synchronizes); with use_graph it then captures the whole device
  * sequence into one HIP graph, which later calls with the same descriptors
- * (same pointers and sizes; values may change) replay without any host
- * synchronization.  out[b] points into plan-owned memory (column indices
- * local to the instance), valid until the next call with other descriptors
- * or spg_plan_destroy.  Calls that overlap on one plan race.
+ * (same pointers and sizes) replay without any host synchronization.  Values
+ * may change between such calls; the row pointers and column indices behind
+ * the descriptors must not (the graph reuses the sizes of the first call).
+ * out[b] points into plan-owned memory (column indices local to the
+ * instance), valid until the next call with other descriptors or
+ * spg_plan_destroy.  Calls that overlap on one plan race.
  * ------------------------------------------------------------------------ */
 spg_status spgemm_galerkin_batched(spg_plan plan, spg_semiring sr, int32_t nb, const spg_csr* RT,
                                    const spg_csr* A, const spg_csr* R, spg_csr* out, int32_t use_graph);

@@ -91,6 +91,8 @@ struct Signature {
 
 constexpr int NAUX = 3;  // helper streams for independent bins
 
+struct GalerkinState;
+
 struct spg_plan_s {
     int device = 0;
     hipStream_t stream = nullptr;  // the caller's stream: every call is ordered on it
@@ -127,6 +129,9 @@ struct spg_plan_s {
     int64_t l_counts[2 * NBINS];
     int64_t l_nfb = 0, l_nexact = 0, l_slots = 0, l_nnz = 0, l_sub_nnz = 0, l_sub_annz = 0;
     spg_semiring l_sr = SPG_SR_PLUS_TIMES_F64;
+
+    // batched Galerkin products (created on first use)
+    GalerkinState* galerkin = nullptr;
 
     // distance-2 independent sets and aggregation
     DevBuf mis_key, mis_m1, mis_cand, mis_new, mis_a1, mis_flags, mis_agg1, mis_ctr;
@@ -1784,19 +1789,10 @@ extern "C" spg_status spgemm_galerkin_copy(spg_plan P, int64_t* row_ptr, int32_t
     return SPG_OK;
 }
 
-// per-plan Galerkin state (kept beside the plan, freed with it)
-#include <map>
-static std::map<spg_plan, GalerkinState*>& galerkin_map() {
-    static std::map<spg_plan, GalerkinState*> m;
-    return m;
-}
+// per-plan Galerkin state (owned by the plan, freed with it)
 static GalerkinState* galerkin_state(spg_plan P) {
-    auto& m = galerkin_map();
-    auto it = m.find(P);
-    if (it != m.end()) return it->second;
-    GalerkinState* G = new (std::nothrow) GalerkinState();
-    if (G) m[P] = G;
-    return G;
+    if (!P->galerkin) P->galerkin = new (std::nothrow) GalerkinState();
+    return P->galerkin;
 }
 static void galerkin_free(GalerkinState* G) {
     if (!G) return;
@@ -1816,11 +1812,8 @@ static void galerkin_free(GalerkinState* G) {
     delete G;
 }
 void spg_release_galerkin(spg_plan P) {
-    auto& m = galerkin_map();
-    auto it = m.find(P);
-    if (it == m.end()) return;
-    galerkin_free(it->second);
-    m.erase(it);
+    galerkin_free(P->galerkin);
+    P->galerkin = nullptr;
 }
 
 // ---------------------------------------------------------------------------
