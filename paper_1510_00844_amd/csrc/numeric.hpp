@@ -313,16 +313,13 @@ __global__ void __launch_bounds__(256) k_split_table(Csr B, int32_t W, int32_t P
     split[idx] = (int32_t)(r - rs);
 }
 
-// PAR = false: one workgroup per row sweeps the P chunks in order.
-// PAR = true: one workgroup per (row, chunk); the chunk's output offset is
-// the row offset plus the counts of the earlier chunks recorded by the
-// symbolic bitmap pass (chunk_cnt, slot heavy_idx[i]), so chunks of one
-// row run side by side and the largest rows do not serialize the kernel.
-template <int SR, int NT, int W, bool PAR, int GM>
+// Rows without a saved bitmap (n above the LDS bitmap): one workgroup per
+// row sweeps the P column chunks of W columns in order, accumulating each
+// chunk densely in LDS and emitting it in column order.
+template <int SR, int NT, int W, int GM>
 __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* rows, int64_t nrows,
                                                   const int64_t* a_beg, const int64_t* a_end,
                                                   const int32_t* split, int32_t P,
-                                                  const int32_t* chunk_cnt, const int32_t* heavy_idx,
                                                   const int64_t* c_rp, int32_t* c_col, void* c_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
@@ -337,25 +334,17 @@ __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* r
     // reads, so later chunks (and later work items) start from zero again
     for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
     for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
-    // work items: rows (PAR = false) or (row, chunk) pairs, grid-stride so
-    // the grid stays small however many chunks there are
-    const int64_t items = PAR ? (int64_t)nrows * P : (int64_t)nrows;
-    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const int64_t i = rows[PAR ? item / P : item];
+    // grid-stride over the rows, so the grid stays small
+    for (int64_t item = blockIdx.x; item < nrows; item += gridDim.x) {
+    const int64_t i = rows[item];
     const int64_t beg = a_beg[i], end = a_end[i];
     int64_t off = c_rp[i];
     const int64_t row_end = c_rp[i + 1];
-    int c_first = 0, c_last = P;
-    if (PAR) {
-        c_first = (int)(item % P);
-        c_last = c_first + 1;
-        const int32_t* cc = chunk_cnt + (int64_t)heavy_idx[i] * P;
-        for (int c = 0; c < c_first; ++c) off += cc[c];
-    }
+    const int c_first = 0, c_last = P;
     // Rows with at most NT entries in the window keep their A entry (column
     // k, start of B(k,:), position reached in B(k,:)) in registers across
     // the chunks, so each chunk costs one split-table load per entry.
-    const bool single = !PAR && end - beg <= NT;
+    const bool single = end - beg <= NT;
     int64_t my_k = 0, my_rs = 0;
     int32_t my_cur = 0;
     if (single && beg + (int64_t)threadIdx.x < end) {

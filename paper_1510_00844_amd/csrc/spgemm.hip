@@ -895,7 +895,6 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                 });
             }));
         } else if (bb == BIN_DENSE) {
-            const bool par = false;
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             P->dense_chunks = chunks;
             const int32_t* split = nullptr;
@@ -913,39 +912,19 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                 }
                 split = P->split.as<int32_t>();
             }
-            const int32_t* cc = P->chunk_save.as<int32_t>();
-            const int32_t* hi = P->heavy_idx.as<int32_t>();
-            const unsigned grid = (unsigned)std::min<int64_t>(par ? nr * chunks : nr, 1 << 16);
-            const std::string name = par ? "num_dense_par" : "num_dense";
+            const unsigned grid = (unsigned)std::min<int64_t>(nr, 1 << 16);
             SPG_TRY(with_gm(P, [&](auto gm) -> spg_status {
                 constexpr int GM = decltype(gm)::value;
-            if (W == 16384) {
-                SPG_TRY(launch(P, name, [&] {
-                    if (par)
-                        k_num_dense<SR, 1024, 16384, true, GM><<<grid, 1024, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
+                return launch(P, "num_dense", [&] {
+                    if (W == 16384)
+                        k_num_dense<SR, 1024, 16384, GM><<<grid, 1024, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, crp, ccol, cval);
+                    else if (W == 8192)
+                        k_num_dense<SR, 512, 8192, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, crp, ccol, cval);
+                    else if (W == 4096)
+                        k_num_dense<SR, 512, 4096, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, crp, ccol, cval);
                     else
-                        k_num_dense<SR, 1024, 16384, false, GM><<<grid, 1024, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
-                }));
-            } else if (W == 8192) {
-                SPG_TRY(launch(P, name, [&] {
-                    if (par)
-                        k_num_dense<SR, 512, 8192, true, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
-                    else
-                        k_num_dense<SR, 512, 8192, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
-                }));
-            } else if (W == 4096) {
-                SPG_TRY(launch(P, name, [&] {
-                    if (par)
-                        k_num_dense<SR, 512, 4096, true, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
-                    else
-                        k_num_dense<SR, 512, 4096, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
-                }));
-            } else {
-                SPG_TRY(launch(P, name, [&] {
-                    k_num_dense<SR, 512, 2048, false, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, cc, hi, crp, ccol, cval);
-                }));
-            }
-                return SPG_OK;
+                        k_num_dense<SR, 512, 2048, GM><<<grid, 512, 0, cs(P)>>>(a, b, rows, nr, ab, ae, split, chunks, crp, ccol, cval);
+                });
             }));
         } else {
             SPG_TRY(num_hash_dispatch<SR>(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, crp, ccol, cval));
