@@ -431,6 +431,48 @@ __device__ inline void stage_bitmap_words(const uint32_t* src, int nw, uint64_t*
     for (int w = threadIdx.x + K * NT; w < nw; w += NT) bw[w] = src[w];
 }
 
+// Packs the staged bitmap words (low half: the bits; high half: the number
+// of set bits in all earlier words) and writes the column cbase + 32 w + b of
+// every set bit, in order, to out[0, cnt).  Each thread scans a contiguous
+// run of words and drops its columns into `acc` (LDS, used as int32 staging:
+// it holds at least cnt accumulators of 4 or 8 bytes); the block then copies
+// them out with consecutive threads on consecutive positions, so the global
+// stores are coalesced, and leaves acc[0, cnt) zero.  Contains barriers.
+template <int NT, typename V>
+__device__ inline void pack_words_write_cols(uint64_t* bw, int nw, int32_t cbase, int32_t cnt, V* acc,
+                                             int32_t* out, int32_t* red) {
+    int32_t* stage = reinterpret_cast<int32_t*>(acc);
+    const int wpt = (nw + NT - 1) / NT;
+    const int w0 = threadIdx.x * wpt;
+    const int w1 = w0 + wpt < nw ? w0 + wpt : nw;
+    int32_t part = 0;
+    for (int w = w0; w < w1; ++w) part += __popc((uint32_t)bw[w]);
+    int32_t dummy;
+    int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
+    for (int w = w0; w < w1; ++w) {
+        uint32_t bits = (uint32_t)bw[w];
+        bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (run < cnt) stage[run] = cbase + w * 32 + b;
+            ++run;
+        }
+    }
+    __syncthreads();
+    // accumulator e holds staged positions [K e, K e + K): one thread reads
+    // them, stores them and clears the accumulator
+    constexpr int K = (int)(sizeof(V) / sizeof(int32_t));
+    const int ne = (cnt + K - 1) / K;
+    for (int e = threadIdx.x; e < ne; e += NT) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (K * e + k < cnt) out[K * e + k] = stage[K * e + k];
+        acc[e] = V(0);
+    }
+    for (int e = ne + threadIdx.x; e < cnt; e += NT) acc[e] = V(0);
+}
+
 // Dynamic LDS: nwords 64-bit words (bits in the low half, count of set bits
 // in all earlier words in the high half), then `cap` accumulators.
 template <int SR, int NT, int GM>
@@ -453,25 +495,7 @@ __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* ro
     const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords;
     stage_bitmap_words<NT>(src, nwords, bw);
     __syncthreads();
-    // each thread owns a contiguous run of words
-    const int wpt = (nwords + NT - 1) / NT;
-    const int w0 = threadIdx.x * wpt;
-    const int w1 = w0 + wpt < nwords ? w0 + wpt : nwords;
-    int32_t part = 0;
-    for (int w = w0; w < w1; ++w) part += __popc((uint32_t)bw[w]);
-    int32_t dummy;
-    int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
-    for (int w = w0; w < w1; ++w) {
-        uint32_t bits = (uint32_t)bw[w];
-        bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1;
-            if (run < cnt) c_col[off + run] = w * 32 + b;
-            ++run;
-        }
-    }
-    for (int r = threadIdx.x; r < cnt; r += NT) acc[r] = S::zero();
+    pack_words_write_cols<NT>(bw, nwords, 0, cnt, acc, c_col + off, red);
     __syncthreads();
     for_each_product_gm<NT, GM>(
         a_beg[i], a_end[i], L,
@@ -556,26 +580,10 @@ __global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const
         const int nw = (item.c1 - item.c0) * WPC;
         const int64_t off = c_rp[i] + item.roff;
         const int32_t cbase = item.c0 * W;
-        // packed words and columns, one contiguous run of words per thread
+        // packed words and columns
         stage_bitmap_words<NT>(src, nw, bw);
         __syncthreads();
-        const int wpt = (nw + NT - 1) / NT;
-        const int w0 = threadIdx.x * wpt;
-        const int w1 = w0 + wpt < nw ? w0 + wpt : nw;
-        int32_t part = 0;
-        for (int w = w0; w < w1; ++w) part += __popc((uint32_t)bw[w]);
-        int32_t dummy;
-        int32_t run = block_exclusive_scan<NT, int32_t>(part, &dummy, red);
-        for (int w = w0; w < w1; ++w) {
-            uint32_t bits = (uint32_t)bw[w];
-            bw[w] = ((uint64_t)(uint32_t)run << 32) | bits;
-            while (bits) {
-                const int b = __ffs(bits) - 1;
-                bits &= bits - 1;
-                if (run < item.cnt) c_col[off + run] = cbase + w * 32 + b;
-                ++run;
-            }
-        }
+        pack_words_write_cols<NT>(bw, nw, cbase, item.cnt < RC ? item.cnt : RC, acc, c_col + off, red);
         __syncthreads();
         const int c0 = item.c0, c1 = item.c1;
         for_each_product_gm<NT, GM>(

@@ -125,12 +125,25 @@ __device__ inline void for_each_product_t(int64_t a_beg, int64_t a_end, ProductL
     }
 }
 
+// 64-bit value of lane l (l wave-uniform).
+__device__ inline int64_t readlane_i64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Same enumeration, mapped for coalesced gathers: each wave takes an equal
 // contiguous range of the batch's products and its lanes take consecutive
 // products, 64 at a time, so one load instruction reads 64 neighbouring B
-// entries.  A step of 64 products that lies inside one segment (the common
-// case for long B rows) needs a single comparison to locate; otherwise each
-// lane binary-searches the segment offsets from the current segment on.
+// entries.  The segment the wave is in is kept in scalar registers (its
+// index, its end, and the offset that turns a product number into a B
+// index), so a step of 64 products that lies inside it costs no LDS access.
+// A step that crosses segment ends reads the offsets of the next 64
+// segments once (lane j: segment ta+j); the non-empty segments starting
+// inside the step form a ballot mask, and each of them, in order, is taken
+// by the lanes at or past its start (a scalar loop over the set bits, no
+// LDS round trips).  Steps with many starts (short B rows) use a binary
+// search over the lanes (shuffles) instead.
 // U steps are gathered (`load(q)`) before any is applied (`apply(t, x)`), so
 // each lane keeps U loads in flight.
 // With COAL = false each thread instead takes its own contiguous range of
@@ -145,6 +158,8 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
         for_each_product_t<NT, U>(a_beg, a_end, L, seg, pre, load, apply);
         return;
     }
+    // segment starts inside one step up to which the scalar loop is used
+    constexpr int LOOP_MAX = 12;
     constexpr int NW = NT / SPG_WAVE;
     const int lane = lane_id();
     // wave-uniform values live in scalar registers (readfirstlane), so the
@@ -169,7 +184,8 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
         const int32_t f0 = wid * span;
         const int32_t f1 = f0 + span < tot ? f0 + span : tot;
         if (f0 < f1) {
-            // segment of the range start
+            // segment of the range start (non-empty: the last one starting
+            // at or before f0)
             int ta = 0;
             {
                 int hi = NT;
@@ -178,6 +194,9 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                     if (__builtin_amdgcn_readfirstlane(L.off[mid]) <= f0) ta = mid; else hi = mid;
                 }
             }
+            // product f of segment ta is B entry ta_rel + f; ta ends at ta_end
+            int64_t ta_rel = readlane_i64(L.bstart[ta] - L.off[ta], 0);
+            int32_t ta_end = __builtin_amdgcn_readfirstlane(L.off[ta + 1]);
             for (int32_t fb = f0; fb < f1; fb += SPG_WAVE * U) {
                 int64_t qq[U];
                 int tt[U];
@@ -189,22 +208,43 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                     ok[u] = f < f1;
                     const int32_t flast = (fs + SPG_WAVE - 1 < f1 ? fs + SPG_WAVE - 1 : f1 - 1);
                     int t = ta;
-                    if (fs < f1 && flast >= __builtin_amdgcn_readfirstlane(L.off[ta + 1])) {
-                        // Segment boundaries inside the step (ta is the last
-                        // segment starting at or before fs).  Lane j holds the
-                        // start of segment ta+j relative to fs; each lane finds
-                        // the last of those 64 starts at or before its product
-                        // by a binary search over the lanes (shuffles).
+                    int64_t rel = ta_rel;
+                    if (fs < f1 && flast >= ta_end) {
+                        // lane j: start (relative to fs), end and B offset of segment ta+j
                         const int j = ta + lane;
-                        const int32_t dj = (j <= NT ? L.off[j] : INT32_MAX) - fs;
-                        const int32_t me = f - fs;
-                        int lo = 0;
-#pragma unroll
-                        for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
-                            const int32_t v = __shfl(dj, lo + step, SPG_WAVE);
-                            if (v <= me) lo += step;
+                        int32_t oj = INT32_MAX, oj1 = INT32_MAX;
+                        int64_t bj = 0;
+                        if (j < NT) {
+                            oj = L.off[j];
+                            oj1 = L.off[j + 1];
+                            bj = L.bstart[j];
                         }
-                        t = ta + lo;
+                        const int32_t dj = oj - fs;
+                        const int64_t rj = bj - oj;
+                        uint64_t starts = __ballot(lane > 0 && dj >= 0 && dj < SPG_WAVE && oj1 > oj);
+                        if (__popcll(starts) <= LOOP_MAX) {
+                            while (starts) {
+                                const int l = __builtin_ctzll(starts);
+                                starts &= starts - 1;
+                                const int32_t dl = __builtin_amdgcn_readlane(dj, l);
+                                const int64_t rl = readlane_i64(rj, l);
+                                if (lane >= dl) {
+                                    t = ta + l;
+                                    rel = rl;
+                                }
+                            }
+                        } else {
+                            // last of the 64 starts at or before this lane
+                            // (empty segments share the start of the next)
+                            int lo = 0;
+#pragma unroll
+                            for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
+                                const int32_t v = __shfl(dj, lo + step, SPG_WAVE);
+                                if (v <= lane) lo += step;
+                            }
+                            t = ta + lo;
+                            rel = __shfl(rj, lo, SPG_WAVE);
+                        }
                         // more than 64 segments start in the step (empty B
                         // rows): the lanes past the 64th search all segments
                         const int32_t o64 =
@@ -216,12 +256,19 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                                 int mid = (t + hi) >> 1;
                                 if (L.off[mid] <= f) t = mid; else hi = mid;
                             }
+                            rel = L.bstart[t] - L.off[t];
                         }
-                        // the next step starts after this step's last product
-                        ta = __builtin_amdgcn_readlane(t, SPG_WAVE - 1);
+                        // the next step starts in the segment of this step's
+                        // last product
+                        const int tn = __builtin_amdgcn_readlane(t, SPG_WAVE - 1);
+                        const int dn = tn - ta;
+                        ta_end = dn < SPG_WAVE ? __builtin_amdgcn_readlane(oj1, dn)
+                                               : __builtin_amdgcn_readfirstlane(L.off[tn + 1]);
+                        ta_rel = readlane_i64(rel, SPG_WAVE - 1);
+                        ta = tn;
                     }
                     tt[u] = t;
-                    qq[u] = L.bstart[t] + (f - L.off[t]);
+                    qq[u] = rel + f;
                 }
                 X x[U];
 #pragma unroll

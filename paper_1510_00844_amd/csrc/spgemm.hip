@@ -249,6 +249,9 @@ static const int RANK_STATIC_LDS_1024 = (int)(8 * 1024 + sizeof(ProductLds<1024>
 static int rank_static_lds(spg_plan P) { return P->opts.rank_block == 1024 ? RANK_STATIC_LDS_1024 : RANK_STATIC_LDS; }
 // rank-chunk items: at most this many outputs and this many column chunks
 static const int RANKC_CAP = 4096;
+// small counters and flags (int32): [0, 17) bin cursors, 32 the CSR check
+// flag, 48 the rank-chunk item count; one size, never reallocated
+static const int SMALL_WORDS = 64;
 
 // ---------------------------------------------------------------------------
 // public helpers
@@ -542,7 +545,7 @@ static spg_status fill_i64(spg_plan P, int64_t* p, int64_t n, int64_t v) {
 
 static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
     if (M->nrows == 0) return SPG_OK;
-    SPG_TRY(P->small_i32.ensure(64, "flags"));
+    SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "flags"));
     int32_t* bad = P->small_i32.as<int32_t>() + 32;
     SPG_TRY(fill_i32(P, bad, 1, 0));
     Csr v = view(M);
@@ -579,7 +582,7 @@ static spg_status ensure_rows(spg_plan P, int64_t m) {
     SPG_TRY(P->bin.ensure(mm, "bin"));
     SPG_TRY(P->lists.ensure(4 * mm, "bin lists"));
     SPG_TRY(P->long_rows.ensure(4 * mm, "long rows"));
-    SPG_TRY(P->small_i32.ensure(64 * 4, "counters"));
+    SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
     SPG_TRY(P->stats.ensure(sizeof(int64_t) * 4 * NBINS, "bin stats"));
     return SPG_OK;
 }
@@ -874,7 +877,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             G = std::max(1, std::min({G, chunks, P->opts.chunk_group}));
             while (G > 1 && (int64_t)G * (W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) --G;
             SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(nr * chunks, 1), "rank items"));
-            SPG_TRY(P->small_i32.ensure(64 * 4, "counters"));
+            SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
             int32_t* nitems = P->small_i32.as<int32_t>() + 48;
             SPG_TRY(fill_i32(P, nitems, 1, 0));
             RankItem* items = P->rank_items.as<RankItem>();
