@@ -99,7 +99,10 @@ typedef struct {
     int32_t serial_heavy;      /* the this-many bins with the most work run back to back on the plan's
                                   stream; the other bins are spread over the streams (0..16) */
     int32_t chunk_unroll;      /* gathers in flight per lane in the rank-chunk items (4 or 8) */
-    int32_t reserved[3];
+    int32_t gather_pipeline;   /* bitmap and rank-chunk kernels in the coalesced 4-step mode keep two
+                                  rounds of gathers in flight (more registers, fewer waves): 0 = when
+                                  the gathered B arrays exceed the 32 MiB of L2, 1 = never, 2 = always */
+    int32_t reserved[2];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;

@@ -150,7 +150,7 @@ __device__ inline int64_t readlane_i64(int64_t v, int l) {
 // products (one search per thread, U consecutive products per step): lanes
 // then touch different segments, which spreads LDS atomics over more
 // addresses at the price of uncoalesced gathers.
-template <int NT, int U, bool COAL = true, class Seg, class Pre, class Load, class Apply>
+template <int NT, int U, bool COAL = true, bool DB = false, class Seg, class Pre, class Load, class Apply>
 __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
                                           Pre pre, Load load, Apply apply) {
     typedef decltype(load((int64_t)0)) X;
@@ -197,17 +197,95 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
             // product f of segment ta is B entry ta_rel + f; ta ends at ta_end
             int64_t ta_rel = readlane_i64(L.bstart[ta] - L.off[ta], 0);
             int32_t ta_end = __builtin_amdgcn_readfirstlane(L.off[ta + 1]);
-            for (int32_t fb = f0; fb < f1; fb += SPG_WAVE * U) {
-                int64_t qq[U];
-                int tt[U];
-                bool ok[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t fs = fb + u * SPG_WAVE;  // first product of this step
+            if constexpr (!DB) {
+                for (int32_t fb = f0; fb < f1; fb += SPG_WAVE * U) {
+                    int64_t qq[U];
+                    int tt[U];
+                    bool ok[U];
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int32_t fs = fb + u * SPG_WAVE;  // first product of this step
+                        const int32_t f = fs + lane;
+                        ok[u] = f < f1;
+                        const int32_t flast = (fs + SPG_WAVE - 1 < f1 ? fs + SPG_WAVE - 1 : f1 - 1);
+                        int t = ta;
+                        int64_t rel = ta_rel;
+                        if (fs < f1 && flast >= ta_end) {
+                            // lane j: start (relative to fs), end and B offset of segment ta+j
+                            const int j = ta + lane;
+                            int32_t oj = INT32_MAX, oj1 = INT32_MAX;
+                            int64_t bj = 0;
+                            if (j < NT) {
+                                oj = L.off[j];
+                                oj1 = L.off[j + 1];
+                                bj = L.bstart[j];
+                            }
+                            const int32_t dj = oj - fs;
+                            const int64_t rj = bj - oj;
+                            uint64_t starts = __ballot(lane > 0 && dj >= 0 && dj < SPG_WAVE && oj1 > oj);
+                            if (__popcll(starts) <= LOOP_MAX) {
+                                while (starts) {
+                                    const int l = __builtin_ctzll(starts);
+                                    starts &= starts - 1;
+                                    const int32_t dl = __builtin_amdgcn_readlane(dj, l);
+                                    const int64_t rl = readlane_i64(rj, l);
+                                    if (lane >= dl) {
+                                        t = ta + l;
+                                        rel = rl;
+                                    }
+                                }
+                            } else {
+                                // last of the 64 starts at or before this lane
+                                // (empty segments share the start of the next)
+                                int lo = 0;
+    #pragma unroll
+                                for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
+                                    const int32_t v = __shfl(dj, lo + step, SPG_WAVE);
+                                    if (v <= lane) lo += step;
+                                }
+                                t = ta + lo;
+                                rel = __shfl(rj, lo, SPG_WAVE);
+                            }
+                            // more than 64 segments start in the step (empty B
+                            // rows): the lanes past the 64th search all segments
+                            const int32_t o64 =
+                                ta + SPG_WAVE <= NT ? __builtin_amdgcn_readfirstlane(L.off[ta + SPG_WAVE]) : INT32_MAX;
+                            if (o64 <= flast && f >= o64) {
+                                int hi = NT;
+                                t = ta + SPG_WAVE;
+                                while (hi - t > 1) {
+                                    int mid = (t + hi) >> 1;
+                                    if (L.off[mid] <= f) t = mid; else hi = mid;
+                                }
+                                rel = L.bstart[t] - L.off[t];
+                            }
+                            // the next step starts in the segment of this step's
+                            // last product
+                            const int tn = __builtin_amdgcn_readlane(t, SPG_WAVE - 1);
+                            const int dn = tn - ta;
+                            ta_end = dn < SPG_WAVE ? __builtin_amdgcn_readlane(oj1, dn)
+                                                   : __builtin_amdgcn_readfirstlane(L.off[tn + 1]);
+                            ta_rel = readlane_i64(rel, SPG_WAVE - 1);
+                            ta = tn;
+                        }
+                        tt[u] = t;
+                        qq[u] = rel + f;
+                    }
+                    X x[U];
+    #pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (ok[u]) x[u] = load(qq[u]);
+    #pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (ok[u]) apply(tt[u], x[u]);
+                }
+            } else {
+                // segment t and B entry q of this lane's product in the step that
+                // starts at product fs; moves the scalar segment state forward
+                auto locate = [&](int32_t fs, int& t, int64_t& q) {
                     const int32_t f = fs + lane;
-                    ok[u] = f < f1;
                     const int32_t flast = (fs + SPG_WAVE - 1 < f1 ? fs + SPG_WAVE - 1 : f1 - 1);
-                    int t = ta;
+                    t = ta;
                     int64_t rel = ta_rel;
                     if (fs < f1 && flast >= ta_end) {
                         // lane j: start (relative to fs), end and B offset of segment ta+j
@@ -237,7 +315,7 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                             // last of the 64 starts at or before this lane
                             // (empty segments share the start of the next)
                             int lo = 0;
-#pragma unroll
+    #pragma unroll
                             for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
                                 const int32_t v = __shfl(dj, lo + step, SPG_WAVE);
                                 if (v <= lane) lo += step;
@@ -267,16 +345,42 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
                         ta_rel = readlane_i64(rel, SPG_WAVE - 1);
                         ta = tn;
                     }
-                    tt[u] = t;
-                    qq[u] = rel + f;
+                    q = rel + f;
+                };
+                // a round: U steps located and their gathers issued
+                auto fetch = [&](int32_t fb, X* x, int* tt, bool* ok) {
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int32_t fs = fb + u * SPG_WAVE;
+                        ok[u] = fs + lane < f1;
+                        int64_t q;
+                        locate(fs, tt[u], q);
+                        if (ok[u]) x[u] = load(q);
+                    }
+                };
+                auto drain = [&](const X* x, const int* tt, const bool* ok) {
+    #pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (ok[u]) apply(tt[u], x[u]);
+                };
+                constexpr int32_t R = SPG_WAVE * U;
+                X xa[U];
+                int ta_[U];
+                bool oa[U];
+                // two rounds in flight: the gathers of the next round are
+                // issued before the products of the current one are applied
+                // (more registers, fewer waves: pays when the gathers miss L2)
+                X xb[U];
+                int tb_[U];
+                bool ob[U];
+                fetch(f0, xa, ta_, oa);
+                for (int32_t fb = f0; fb < f1; fb += 2 * R) {
+                    if (fb + R < f1) fetch(fb + R, xb, tb_, ob);
+                    drain(xa, ta_, oa);
+                    if (fb + R >= f1) break;
+                    if (fb + 2 * R < f1) fetch(fb + 2 * R, xa, ta_, oa);
+                    drain(xb, tb_, ob);
                 }
-                X x[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) x[u] = load(qq[u]);
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) apply(tt[u], x[u]);
             }
         }
         __syncthreads();
@@ -286,12 +390,14 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
 // Gather mode of the heavy-row kernels (a tuning choice):
 //   0: coalesced, 4 steps in flight   1: coalesced, 8 steps in flight
 //   2: per-thread ranges, 4 in flight 3: per-thread ranges, 8 in flight
+//   4: coalesced, two rounds of 4 steps in flight (double-buffered)
 template <int NT, int GM, class Seg, class Pre, class Load, class Apply>
 __device__ inline void for_each_product_gm(int64_t a_beg, int64_t a_end, ProductLds<NT>& L, Seg seg,
                                            Pre pre, Load load, Apply apply) {
     if constexpr (GM == 0) for_each_product_u<NT, 4, true>(a_beg, a_end, L, seg, pre, load, apply);
     else if constexpr (GM == 1) for_each_product_u<NT, 8, true>(a_beg, a_end, L, seg, pre, load, apply);
     else if constexpr (GM == 2) for_each_product_u<NT, 4, false>(a_beg, a_end, L, seg, pre, load, apply);
+    else if constexpr (GM == 4) for_each_product_u<NT, 4, true, true>(a_beg, a_end, L, seg, pre, load, apply);
     else for_each_product_u<NT, 8, false>(a_beg, a_end, L, seg, pre, load, apply);
 }
 

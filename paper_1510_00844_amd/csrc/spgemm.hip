@@ -315,26 +315,53 @@ static void set_lds_attributes(spg_plan P) {
     hipFuncSetAttribute((const void*)k_learned_fused<SR_BOOL, 512, GM>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
 }
 
+// gather mode 4 exists for the bitmap and rank-chunk kernels only
+static void set_lds_attributes_pipelined(spg_plan P) {
+    const int dyn_bitmap = std::max(0, P->max_lds - (int)sizeof(ProductLds<512>) - 64 - 4 * MAX_CHUNKS);
+    const int dyn_rank = std::max(0, P->max_lds - RANK_STATIC_LDS);
+    hipFuncSetAttribute((const void*)k_sym_bitmap<512, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_bitmap);
+    hipFuncSetAttribute((const void*)k_num_rankc<SR_F64, 512, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rankc<SR_I64, 512, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+    hipFuncSetAttribute((const void*)k_num_rankc<SR_BOOL, 512, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_rank);
+}
+
 static int gather_mode(int map, int unroll) { return (map == 2 ? 2 : 0) + (unroll == 8 ? 1 : 0); }
 
+// Double-buffered gathers (gather mode 4) for the bitmap and rank-chunk
+// kernels: chosen by opts.gather_pipeline, automatically when the B arrays
+// those kernels gather exceed the combined L2 of the 8 XCDs (4 MiB each).
+static const int64_t L2_TOTAL_BYTES = 8ll * 4 * 1024 * 1024;
+static bool pipelined(spg_plan P, const Csr& b, int64_t bytes_per_entry) {
+    if (P->opts.gather_pipeline == 1) return false;
+    if (P->opts.gather_pipeline == 2) return true;
+    return b.nnz * bytes_per_entry > L2_TOTAL_BYTES;
+}
+
 // Call f(std::integral_constant<int, GM>) for the plan's gather mode of the
-// numeric (sym = false) or symbolic heavy-row kernels.
-template <class F>
-static spg_status with_gm(spg_plan P, F&& f, bool sym = false) {
+// numeric (sym = false) or symbolic heavy-row kernels; pipe turns the
+// coalesced 4-step mode into its double-buffered form (mode 4).
+template <bool PIPE = false, class F>
+static spg_status with_gm(spg_plan P, F&& f, bool sym = false, bool pipe = false) {
     const int gm = sym ? gather_mode(P->opts.sym_gather_map, P->opts.sym_unroll)
                        : gather_mode(P->opts.gather_map, P->opts.unroll);
     switch (gm) {
-        case 0: return f(std::integral_constant<int, 0>());
+        case 0:
+            if constexpr (PIPE)
+                if (pipe) return f(std::integral_constant<int, 4>());
+            return f(std::integral_constant<int, 0>());
         case 1: return f(std::integral_constant<int, 1>());
         case 2: return f(std::integral_constant<int, 2>());
         default: return f(std::integral_constant<int, 3>());
     }
 }
 
-template <class F>
-static spg_status with_gm_u(spg_plan P, int map, int unroll, F&& f) {
+template <bool PIPE = false, class F>
+static spg_status with_gm_u(spg_plan P, int map, int unroll, F&& f, bool pipe = false) {
     switch (gather_mode(map, unroll)) {
-        case 0: return f(std::integral_constant<int, 0>());
+        case 0:
+            if constexpr (PIPE)
+                if (pipe) return f(std::integral_constant<int, 4>());
+            return f(std::integral_constant<int, 0>());
         case 1: return f(std::integral_constant<int, 1>());
         case 2: return f(std::integral_constant<int, 2>());
         default: return f(std::integral_constant<int, 3>());
@@ -384,6 +411,10 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     if (P->opts.hash_max_nnz < 1 || P->opts.hash_max_nnz > 4096) {
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
+    }
+    if (P->opts.gather_pipeline < 0 || P->opts.gather_pipeline > 2) {
+        delete P;
+        return fail(SPG_ERR_ARG, "gather_pipeline must be 0 (by size), 1 (off) or 2 (on)");
     }
     if (P->opts.chunk_unroll != 4 && P->opts.chunk_unroll != 8) {
         delete P;
@@ -438,6 +469,7 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     set_lds_attributes<1>(P);
     set_lds_attributes<2>(P);
     set_lds_attributes<3>(P);
+    set_lds_attributes_pipelined(P);
     hipGetLastError();
     *out = P;
     return SPG_OK;
@@ -729,13 +761,13 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                 SPG_TRY(P->chunk_save.ensure((size_t)nr * nchunks * 4, "chunk counts"));
                 csave = P->chunk_save.as<int32_t>();
             }
-            SPG_TRY(with_gm(P, [&](auto gm) {
+            SPG_TRY(with_gm<true>(P, [&](auto gm) {
                 return launch(P, "sym_bitmap", [&] {
                     k_sym_bitmap<512, decltype(gm)::value><<<(unsigned)nr, 512, (size_t)nwords * 4, cs(P)>>>(
                         a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords, save, hidx, csave,
                         W / 32, nchunks);
                 });
-            }, true));
+            }, true, pipelined(P, b, 4)));
         } else {
             SPG_TRY(sym_hash_dispatch(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, cnt));
         }
@@ -890,13 +922,13 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
             const size_t lds = (size_t)G * (W / 32) * 8 + (size_t)RC * sizeof(typename Sr<SR>::acc_t);
             const int32_t* split = chunks > 1 ? P->split.as<int32_t>() : nullptr;
             const unsigned grid = (unsigned)std::min<int64_t>(nr * chunks, 256 * 8);
-            SPG_TRY(with_gm_u(P, P->opts.gather_map, P->opts.chunk_unroll, [&](auto gm) {
+            SPG_TRY(with_gm_u<true>(P, P->opts.gather_map, P->opts.chunk_unroll, [&](auto gm) {
                 return launch(P, "num_rankc", [&] {
                     k_num_rankc<SR, 512, decltype(gm)::value><<<grid, 512, lds, cs(P)>>>(
                         a, b, W, rows, ab, ae, P->bm_save.as<uint32_t>(), hi, nwords, split, chunks, items, nitems, RC, G,
                         crp, ccol, cval);
                 });
-            }));
+            }, pipelined(P, b, 4 + (int64_t)sizeof(typename Sr<SR>::acc_t))));
         } else if (bb == BIN_DENSE) {
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             P->dense_chunks = chunks;

@@ -315,7 +315,8 @@ def test_rmat_s19_c5_sampled(plan):
     dict(hash_max_nnz=1024), dict(hash_max_nnz=512, chunk_min_nnz=256), dict(chunk_unroll=8),
     dict(serial_heavy=2), dict(serial_heavy=16, streams=2), dict(streams=1, rank_block=512),
     dict(rank_max_nnz=16384, rank_block=512), dict(rank_max_nnz=1, chunk_group=1),
-    dict(gather_map=2, unroll=8, sym_gather_map=2, sym_unroll=8), dict(small_max_flops=1, hash_max_flops=128)])
+    dict(gather_map=2, unroll=8, sym_gather_map=2, sym_unroll=8), dict(small_max_flops=1, hash_max_flops=128),
+    dict(gather_pipeline=2), dict(gather_pipeline=2, rank_max_nnz=1, dense_chunk_cols=2048)])
 def test_option_variants(opts):
     """Every tuning option gives the oracle's product (R-MAT G500 scale 13,
     FP64, plus an INT64 run for the exact values)."""
