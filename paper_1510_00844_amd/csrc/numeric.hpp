@@ -531,26 +531,37 @@ struct RankItem {
 __global__ void __launch_bounds__(256) k_rank_items(const int32_t* rows, int32_t nrows, const int32_t* heavy_idx,
                                                     const int32_t* chunk_cnt, int32_t P, int32_t RC, int32_t G,
                                                     RankItem* items, int32_t* nitems) {
+    __shared__ int32_t tmp[256 / SPG_WAVE + 1];
+    __shared__ int32_t s_base;
     const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= nrows) return;
-    const int32_t* cc = chunk_cnt + (int64_t)heavy_idx[rows[r]] * P;
-    int64_t roff = 0;
-    int c0 = 0;
-    while (c0 < P) {
-        int c1 = c0;
-        int32_t n = 0;
-        while (c1 < P && c1 - c0 < G && n + cc[c1] <= RC) n += cc[c1++];
-        if (c1 == c0) {  // a chunk above RC (the host keeps RC >= W): take it alone, always progress
-            n = cc[c0];
-            c1 = c0 + 1;
+    const int32_t* cc = r < nrows ? chunk_cnt + (int64_t)heavy_idx[rows[r]] * P : nullptr;
+    // the greedy grouping of the row's chunks, walked twice: to count the
+    // items (one global add per workgroup reserves their slots), then to
+    // write them
+    auto walk = [&](auto emit) {
+        int64_t roff = 0;
+        int c0 = 0;
+        while (c0 < P) {
+            int c1 = c0;
+            int32_t n = 0;
+            while (c1 < P && c1 - c0 < G && n + cc[c1] <= RC) n += cc[c1++];
+            if (c1 == c0) {  // a chunk above RC (the host keeps RC >= W): take it alone, always progress
+                n = cc[c0];
+                c1 = c0 + 1;
+            }
+            if (n > 0) emit(c0, c1, n, roff);
+            roff += n;
+            c0 = c1;
         }
-        if (n > 0) {
-            const int slot = atomicAdd(nitems, 1);
-            items[slot] = RankItem{r, c0, c1, n, roff};
-        }
-        roff += n;
-        c0 = c1;
-    }
+    };
+    int32_t mine = 0;
+    if (cc) walk([&](int, int, int32_t, int64_t) { ++mine; });
+    int32_t total;
+    int32_t slot = block_exclusive_scan<256, int32_t>(mine, &total, tmp);
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(nitems, total) : 0;
+    __syncthreads();
+    slot += s_base;
+    if (cc) walk([&](int c0, int c1, int32_t n, int64_t roff) { items[slot++] = RankItem{r, c0, c1, n, roff}; });
 }
 
 // Dynamic LDS: G*W/32 packed words (prefix << 32 | bits), then RC values.
