@@ -179,12 +179,18 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
         [&](int, uint32_t j) { atomicOr(&bm[j >> 5], 1u << (j & 31)); });
     int32_t mine = 0;
     uint32_t* dst = bm_save ? bm_save + (int64_t)blockIdx.x * nwords : nullptr;
-    for (int t = threadIdx.x; t < nwords; t += NT) {
-        const uint32_t w = bm[t];
+    // a wave's 64 consecutive words lie in one chunk (chunk_words is a
+    // multiple of 64): the wave sums its counts and adds them once
+    for (int t0 = threadIdx.x - lane_id(); t0 < nwords; t0 += NT) {
+        const int t = t0 + lane_id();
+        const uint32_t w = t < nwords ? bm[t] : 0u;
         const int pc = __popc(w);
         mine += pc;
-        if (dst) dst[t] = w;
-        if (chunk_save && pc) atomicAdd(&s_chunk[t / chunk_words], pc);
+        if (dst && t < nwords) dst[t] = w;
+        if (chunk_save) {
+            const int cs = wave_reduce_add(pc);
+            if (lane_id() == 0 && cs) atomicAdd(&s_chunk[t0 / chunk_words], cs);
+        }
     }
     int32_t total = block_reduce_add<NT, int32_t>(mine, red);  // barriers: s_chunk complete
     if (threadIdx.x == 0) {
