@@ -306,4 +306,55 @@ __global__ void __launch_bounds__(256) k_bin_scatter(int64_t m, const uint8_t* b
     if (b >= 0) lists[s_base[b] + local] = (int32_t)i;
 }
 
+// Longest-processing-time order of one bin's row list: rows with more
+// products first, so that the heaviest workgroups start early and the end of
+// the launch is not held up by a large row that started last.  A counting
+// sort over 256 keys (8 per power of two of the products: rows within about
+// 12% of each other share a key): histogram, scan, scatter.
+constexpr int LPT_KEYS = 256;
+__device__ inline int lpt_key(int64_t w) {
+    if (w < 1) w = 1;
+    const int e = 63 - __clzll((unsigned long long)w);  // floor(log2 w)
+    const int frac = e >= 3 ? (int)((w >> (e - 3)) & 7) : (int)((w << (3 - e)) & 7);
+    const int k = e * 8 + frac;
+    return LPT_KEYS - 1 - (k < LPT_KEYS - 1 ? k : LPT_KEYS - 1);  // more work: smaller key
+}
+
+__global__ void __launch_bounds__(256) k_lpt_hist(const int32_t* rows, int64_t n, const int64_t* work,
+                                                  int32_t* hist) {
+    __shared__ int32_t s_h[LPT_KEYS];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < n) atomicAdd(&s_h[lpt_key(work[rows[r]])], 1);
+    __syncthreads();
+    if (s_h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], s_h[threadIdx.x]);
+}
+
+// one workgroup of LPT_KEYS threads: counts -> exclusive offsets, in place
+__global__ void __launch_bounds__(LPT_KEYS) k_lpt_scan(int32_t* hist) {
+    __shared__ int32_t tmp[LPT_KEYS / SPG_WAVE + 1];
+    int32_t total;
+    const int32_t v = hist[threadIdx.x];
+    hist[threadIdx.x] = block_exclusive_scan<LPT_KEYS, int32_t>(v, &total, tmp);
+}
+
+__global__ void __launch_bounds__(256) k_lpt_scatter(const int32_t* rows, int64_t n, const int64_t* work,
+                                                     int32_t* cursor, int32_t* out) {
+    __shared__ int32_t s_cnt[LPT_KEYS], s_base[LPT_KEYS];
+    s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int key = 0, local = 0, row = 0;
+    if (r < n) {
+        row = rows[r];
+        key = lpt_key(work[row]);
+        local = atomicAdd(&s_cnt[key], 1);
+    }
+    __syncthreads();
+    if (s_cnt[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (r < n) out[s_base[key] + local] = row;
+}
+
 }  // namespace spg

@@ -105,6 +105,7 @@ struct spg_plan_s {
     // per-row state of the current product
     DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
     DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save, rank_items;
+    DevBuf lpt_hist, lpt_tmp;  // ordering of heavy bins by work
     int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
     LayerDesc* h_layers = nullptr; // pinned staging for merge descriptors
     int h_layers_cap = 0;
@@ -484,6 +485,7 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
     for (DevBuf* b : {&P->a_beg, &P->a_end, &P->flops, &P->maxb, &P->bin, &P->lists, &P->long_rows,
                       &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
                       &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save, &P->rank_items,
+                      &P->lpt_hist, &P->lpt_tmp,
                       &P->lcap, &P->lcnt, &P->slot, &P->pcol, &P->pval, &P->fb_list, &P->fb_redo, &P->sub_rp,
                       &P->sub_col, &P->sub_val, &P->sub_crp, &P->sub_ccol, &P->sub_cval, &P->mlp_tmp,
                       &P->mis_key, &P->mis_m1, &P->mis_cand, &P->mis_new, &P->mis_a1, &P->mis_flags, &P->mis_agg1,
@@ -575,6 +577,26 @@ static spg_status fill_i64(spg_plan P, int64_t* p, int64_t n, int64_t v) {
     return launch(P, "fill", [&] { k_fill_i64<<<grid_for(n, 256), 256, 0, cs(P)>>>(p, n, v); });
 }
 
+// Reorders bin bb's row list (lists + off, nr entries) by decreasing
+// products, on the current stream (counting sort over LPT_KEYS keys).  Each
+// bin has its own histogram and staging range (sized by ensure_rows), so
+// bins on different streams do not share scratch.
+static spg_status order_by_work(spg_plan P, int bb, int64_t off, int64_t nr) {
+    if (nr < 2) return SPG_OK;
+    int32_t* rows = P->lists.as<int32_t>() + off;
+    int32_t* hist = P->lpt_hist.as<int32_t>() + (int64_t)bb * LPT_KEYS;
+    int32_t* tmp = P->lpt_tmp.as<int32_t>() + off;
+    const int64_t* work = P->flops.as<int64_t>();
+    SPG_TRY(fill_i32(P, hist, LPT_KEYS, 0));
+    SPG_TRY(launch(P, "work_order", [&] { k_lpt_hist<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, work, hist); }));
+    SPG_TRY(launch(P, "work_order", [&] { k_lpt_scan<<<1, LPT_KEYS, 0, cs(P)>>>(hist); }));
+    SPG_TRY(launch(P, "work_order", [&] {
+        k_lpt_scatter<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, work, hist, tmp);
+    }));
+    HIP_TRY(hipMemcpyAsync(rows, tmp, sizeof(int32_t) * (size_t)nr, hipMemcpyDeviceToDevice, cs(P)));
+    return SPG_OK;
+}
+
 static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
     if (M->nrows == 0) return SPG_OK;
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "flags"));
@@ -613,6 +635,8 @@ static spg_status ensure_rows(spg_plan P, int64_t m) {
     SPG_TRY(P->maxb.ensure(4 * mm, "maxb"));
     SPG_TRY(P->bin.ensure(mm, "bin"));
     SPG_TRY(P->lists.ensure(4 * mm, "bin lists"));
+    SPG_TRY(P->lpt_tmp.ensure(4 * mm, "work order"));
+    SPG_TRY(P->lpt_hist.ensure(sizeof(int32_t) * NBINS * LPT_KEYS, "work order"));
     SPG_TRY(P->long_rows.ensure(4 * mm, "long rows"));
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
     SPG_TRY(P->stats.ensure(sizeof(int64_t) * 4 * NBINS, "bin stats"));
@@ -743,6 +767,7 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                                                                      P->a_end.as<int64_t>(), cnt);
             }));
         } else if (bb == BIN_DENSE) {
+            SPG_TRY(order_by_work(P, bb, bin_off[bb], nr));
             const int32_t nwords = (int32_t)std::min<int64_t>((n + 31) / 32, 1 << 14);
             uint32_t* save = nullptr;
             int32_t* hidx = nullptr;
@@ -881,6 +906,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                 k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
             }));
         } else if (bb >= BIN_RANK0) {
+            SPG_TRY(order_by_work(P, bb, bin_off[bb], nr));
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
             const int64_t cap = 4096ll << (bb - BIN_RANK0);
             const size_t lds = (size_t)nwords * 8 + (size_t)cap * sizeof(typename Sr<SR>::acc_t);
@@ -897,6 +923,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                 });
             }));
         } else if (bb == BIN_DENSE_PAR) {
+            SPG_TRY(order_by_work(P, bb, bin_off[bb], nr));
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             // an item holds at least one whole chunk (<= W outputs); group as
             // many chunks as the LDS allows, up to RANKC_GROUP
