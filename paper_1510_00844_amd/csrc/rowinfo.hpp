@@ -306,55 +306,72 @@ __global__ void __launch_bounds__(256) k_bin_scatter(int64_t m, const uint8_t* b
     if (b >= 0) lists[s_base[b] + local] = (int32_t)i;
 }
 
-// Longest-processing-time order of one bin's row list: rows with more
-// products first, so that the heaviest workgroups start early and the end of
-// the launch is not held up by a large row that started last.  A counting
-// sort over 256 keys (8 per power of two of the products: rows within about
-// 12% of each other share a key): histogram, scan, scatter.
+// Longest-processing-time order of the row lists of a run of consecutive
+// bins [b_lo, b_lo + nb): within each bin, rows with more products first,
+// so that the heaviest workgroups start early and the end of a launch is not
+// held up by a large row that started last.  The bins' lists are contiguous,
+// so one counting sort over the run with key (bin - b_lo, work class) keeps
+// every bin in place; 256 work classes per bin, 8 per power of two of the
+// products (rows within about 12% of each other share a class).
 constexpr int LPT_KEYS = 256;
-__device__ inline int lpt_key(int64_t w) {
+constexpr int LPT_MAX_BINS = 8;
+__device__ inline int lpt_class(int64_t w) {
     if (w < 1) w = 1;
     const int e = 63 - __clzll((unsigned long long)w);  // floor(log2 w)
     const int frac = e >= 3 ? (int)((w >> (e - 3)) & 7) : (int)((w << (3 - e)) & 7);
     const int k = e * 8 + frac;
-    return LPT_KEYS - 1 - (k < LPT_KEYS - 1 ? k : LPT_KEYS - 1);  // more work: smaller key
+    return LPT_KEYS - 1 - (k < LPT_KEYS - 1 ? k : LPT_KEYS - 1);  // more work: smaller class
+}
+__device__ inline int lpt_key(int32_t row, const uint8_t* bin, int b_lo, const int64_t* work) {
+    return ((int)bin[row] - b_lo) * LPT_KEYS + lpt_class(work[row]);
 }
 
-__global__ void __launch_bounds__(256) k_lpt_hist(const int32_t* rows, int64_t n, const int64_t* work,
-                                                  int32_t* hist) {
-    __shared__ int32_t s_h[LPT_KEYS];
-    s_h[threadIdx.x] = 0;
+__global__ void __launch_bounds__(256) k_lpt_hist(const int32_t* rows, int64_t n, const uint8_t* bin, int b_lo,
+                                                  int nk, const int64_t* work, int32_t* hist) {
+    __shared__ int32_t s_h[LPT_KEYS * LPT_MAX_BINS];
+    for (int k = threadIdx.x; k < nk; k += 256) s_h[k] = 0;
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r < n) atomicAdd(&s_h[lpt_key(work[rows[r]])], 1);
+    if (r < n) atomicAdd(&s_h[lpt_key(rows[r], bin, b_lo, work)], 1);
     __syncthreads();
-    if (s_h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], s_h[threadIdx.x]);
+    for (int k = threadIdx.x; k < nk; k += 256)
+        if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
 }
 
-// one workgroup of LPT_KEYS threads: counts -> exclusive offsets, in place
-__global__ void __launch_bounds__(LPT_KEYS) k_lpt_scan(int32_t* hist) {
-    __shared__ int32_t tmp[LPT_KEYS / SPG_WAVE + 1];
+// one workgroup: counts -> exclusive offsets, in place (nk <= 256 * LPT_MAX_BINS;
+// thread t owns keys [t * per, (t + 1) * per))
+__global__ void __launch_bounds__(256) k_lpt_scan(int32_t* hist, int nk) {
+    __shared__ int32_t tmp[256 / SPG_WAVE + 1];
+    const int per = (nk + 255) / 256;
+    const int k0 = threadIdx.x * per;
+    int32_t part = 0;
+    for (int k = k0; k < k0 + per && k < nk; ++k) part += hist[k];
     int32_t total;
-    const int32_t v = hist[threadIdx.x];
-    hist[threadIdx.x] = block_exclusive_scan<LPT_KEYS, int32_t>(v, &total, tmp);
+    int32_t run = block_exclusive_scan<256, int32_t>(part, &total, tmp);
+    for (int k = k0; k < k0 + per && k < nk; ++k) {
+        const int32_t v = hist[k];
+        hist[k] = run;
+        run += v;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_lpt_scatter(const int32_t* rows, int64_t n, const int64_t* work,
-                                                     int32_t* cursor, int32_t* out) {
-    __shared__ int32_t s_cnt[LPT_KEYS], s_base[LPT_KEYS];
-    s_cnt[threadIdx.x] = 0;
+__global__ void __launch_bounds__(256) k_lpt_scatter(const int32_t* rows, int64_t n, const uint8_t* bin, int b_lo,
+                                                     int nk, const int64_t* work, int32_t* cursor, int32_t* out) {
+    __shared__ int32_t s_cnt[LPT_KEYS * LPT_MAX_BINS];
+    for (int k = threadIdx.x; k < nk; k += 256) s_cnt[k] = 0;
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int key = 0, local = 0, row = 0;
     if (r < n) {
         row = rows[r];
-        key = lpt_key(work[row]);
+        key = lpt_key(row, bin, b_lo, work);
         local = atomicAdd(&s_cnt[key], 1);
     }
     __syncthreads();
-    if (s_cnt[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], s_cnt[threadIdx.x]);
+    for (int k = threadIdx.x; k < nk; k += 256)
+        if (s_cnt[k]) s_cnt[k] = atomicAdd(&cursor[k], s_cnt[k]);  // now the block's base for key k
     __syncthreads();
-    if (r < n) out[s_base[key] + local] = row;
+    if (r < n) out[s_cnt[key] + local] = row;
 }
 
 }  // namespace spg

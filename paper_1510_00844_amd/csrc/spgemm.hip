@@ -577,21 +577,26 @@ static spg_status fill_i64(spg_plan P, int64_t* p, int64_t n, int64_t v) {
     return launch(P, "fill", [&] { k_fill_i64<<<grid_for(n, 256), 256, 0, cs(P)>>>(p, n, v); });
 }
 
-// Reorders bin bb's row list (lists + off, nr entries) by decreasing
-// products, on the current stream (counting sort over LPT_KEYS keys).  Each
-// bin has its own histogram and staging range (sized by ensure_rows), so
-// bins on different streams do not share scratch.
-static spg_status order_by_work(spg_plan P, int bb, int64_t off, int64_t nr) {
+// Orders the row lists of bins [b_lo, b_hi) (contiguous in P->lists from
+// bin_off[b_lo]) by decreasing products within each bin, on the plan's
+// stream before the bins are launched (counting sort, three kernels).
+static_assert(NBINS - BIN_DENSE_PAR <= LPT_MAX_BINS, "the heavy numeric bins fit one work ordering");
+static spg_status order_by_work(spg_plan P, int b_lo, int b_hi, const int64_t* bin_off) {
+    const int64_t off = bin_off[b_lo], nr = bin_off[b_hi] - off;
     if (nr < 2) return SPG_OK;
+    const int nk = (b_hi - b_lo) * LPT_KEYS;
     int32_t* rows = P->lists.as<int32_t>() + off;
-    int32_t* hist = P->lpt_hist.as<int32_t>() + (int64_t)bb * LPT_KEYS;
-    int32_t* tmp = P->lpt_tmp.as<int32_t>() + off;
+    int32_t* hist = P->lpt_hist.as<int32_t>();
+    int32_t* tmp = P->lpt_tmp.as<int32_t>();
     const int64_t* work = P->flops.as<int64_t>();
-    SPG_TRY(fill_i32(P, hist, LPT_KEYS, 0));
-    SPG_TRY(launch(P, "work_order", [&] { k_lpt_hist<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, work, hist); }));
-    SPG_TRY(launch(P, "work_order", [&] { k_lpt_scan<<<1, LPT_KEYS, 0, cs(P)>>>(hist); }));
+    const uint8_t* bin = P->bin.as<uint8_t>();
+    SPG_TRY(fill_i32(P, hist, nk, 0));
     SPG_TRY(launch(P, "work_order", [&] {
-        k_lpt_scatter<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, work, hist, tmp);
+        k_lpt_hist<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, bin, b_lo, nk, work, hist);
+    }));
+    SPG_TRY(launch(P, "work_order", [&] { k_lpt_scan<<<1, 256, 0, cs(P)>>>(hist, nk); }));
+    SPG_TRY(launch(P, "work_order", [&] {
+        k_lpt_scatter<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, bin, b_lo, nk, work, hist, tmp);
     }));
     HIP_TRY(hipMemcpyAsync(rows, tmp, sizeof(int32_t) * (size_t)nr, hipMemcpyDeviceToDevice, cs(P)));
     return SPG_OK;
@@ -636,7 +641,7 @@ static spg_status ensure_rows(spg_plan P, int64_t m) {
     SPG_TRY(P->bin.ensure(mm, "bin"));
     SPG_TRY(P->lists.ensure(4 * mm, "bin lists"));
     SPG_TRY(P->lpt_tmp.ensure(4 * mm, "work order"));
-    SPG_TRY(P->lpt_hist.ensure(sizeof(int32_t) * NBINS * LPT_KEYS, "work order"));
+    SPG_TRY(P->lpt_hist.ensure(sizeof(int32_t) * LPT_MAX_BINS * LPT_KEYS, "work order"));
     SPG_TRY(P->long_rows.ensure(4 * mm, "long rows"));
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
     SPG_TRY(P->stats.ensure(sizeof(int64_t) * 4 * NBINS, "bin stats"));
@@ -752,6 +757,8 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     int64_t bin_off[NBINS + 1];
     bin_off[0] = 0;
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->sym_counts[x];
+    // the bitmap rows, heaviest first
+    if (P->sym_counts[BIN_DENSE] > 1) SPG_TRY(order_by_work(P, BIN_DENSE, BIN_DENSE + 1, bin_off));
     SPG_TRY(fork_streams(P));
     const std::vector<int> sym_order = bins_by_work(P->sym_counts, P->sym_counts + NBINS);
     StreamLoad sload(P, P->sym_counts);
@@ -767,7 +774,6 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
                                                                      P->a_end.as<int64_t>(), cnt);
             }));
         } else if (bb == BIN_DENSE) {
-            SPG_TRY(order_by_work(P, bb, bin_off[bb], nr));
             const int32_t nwords = (int32_t)std::min<int64_t>((n + 31) / 32, 1 << 14);
             uint32_t* save = nullptr;
             int32_t* hidx = nullptr;
@@ -888,6 +894,10 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
         }
         split_built = true;
     }
+    // rank-chunk, dense and rank rows (bins 11..15, contiguous), heaviest first
+    if (P->num_counts[BIN_DENSE_PAR] + P->num_counts[BIN_DENSE] + P->num_counts[BIN_RANK0] +
+            P->num_counts[BIN_RANK0 + 1] + P->num_counts[BIN_RANK0 + 2] > 1)
+        SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, bin_off));
     SPG_TRY(fork_streams(P));
     const std::vector<int> num_order = bins_by_work(P->num_counts, P->num_counts + NBINS);
     StreamLoad nload(P, P->num_counts);
@@ -906,7 +916,6 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                 k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
             }));
         } else if (bb >= BIN_RANK0) {
-            SPG_TRY(order_by_work(P, bb, bin_off[bb], nr));
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
             const int64_t cap = 4096ll << (bb - BIN_RANK0);
             const size_t lds = (size_t)nwords * 8 + (size_t)cap * sizeof(typename Sr<SR>::acc_t);
@@ -923,7 +932,6 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32
                 });
             }));
         } else if (bb == BIN_DENSE_PAR) {
-            SPG_TRY(order_by_work(P, bb, bin_off[bb], nr));
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             // an item holds at least one whole chunk (<= W outputs); group as
             // many chunks as the LDS allows, up to RANKC_GROUP
