@@ -206,7 +206,9 @@ static spg_status join_streams(spg_plan P) {
 // serial_heavy bins stay on the plan's stream.  Work = products + 32 per row.
 // Streams in use: at most opts.streams, and no more than the number of bins
 // holding at least 5% of the work (more streams than heavy bins only splits
-// the GPU between a heavy kernel and small ones without shortening it).
+// the GPU between heavy kernels and small ones without shortening them), but
+// two whenever two bins have rows: the light bins then run beside the
+// heaviest one instead of after it.
 static double bin_work(const int64_t* counts, int bin) {
     return (double)counts[NBINS + bin] + 32.0 * (double)counts[bin];
 }
@@ -219,7 +221,9 @@ struct StreamLoad {
         int heavy = 0;
         for (int b = 1; b < NBINS; ++b)
             if (counts[b] > 0 && bin_work(counts, b) >= 0.05 * total) ++heavy;
-        nstreams = std::max(1, std::min(P->opts.streams, heavy));
+        int nonempty = 0;
+        for (int b = 1; b < NBINS; ++b) nonempty += counts[b] > 0;
+        nstreams = std::max(1, std::min(P->opts.streams, std::max(heavy, nonempty > 1 ? 2 : 1)));
     }
 };
 static void use_stream(spg_plan P, StreamLoad& L, int pos, const int64_t* counts, int bin) {
