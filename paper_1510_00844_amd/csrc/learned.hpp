@@ -248,6 +248,14 @@ __global__ void __launch_bounds__(256) k_scatter_counts(const int32_t* list, int
     if (r < nl) cnt[list[r]] = sub_rp[r + 1] - sub_rp[r];
 }
 
+// Final output offset of every listed row (the recomputed rows then write
+// straight into the full product).
+__global__ void __launch_bounds__(256) k_gather_offsets(const int32_t* list, int32_t nl, const int64_t* c_rp,
+                                                        int64_t* pos) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < nl) pos[r] = c_rp[list[r]];
+}
+
 // Compaction: one wave per row copies `len` entries from src offset to the
 // final offset.  mode 0: rows 0..m-1 from their slots, skipping redo rows;
 // mode 1: listed rows from the recomputed compact result.

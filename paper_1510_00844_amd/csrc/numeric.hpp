@@ -30,10 +30,21 @@ struct BEntry {
     V val;
 };
 
+// Where a row's output goes: its count is rp[i+1] - rp[i]; it starts at
+// pos[i] when pos is given (rows of a gathered sub-product written straight
+// into the full product), else at rp[i].
+struct OutRows {
+    const int64_t* rp;
+    const int64_t* pos;
+    __host__ __device__ OutRows(const int64_t* r, const int64_t* p = nullptr) : rp(r), pos(p) {}
+    __device__ int64_t off(int64_t i) const { return pos ? pos[i] : rp[i]; }
+    __device__ int64_t count(int64_t i) const { return rp[i + 1] - rp[i]; }
+};
+
 // One wave per row, rows given by a list.
 template <int SR>
 __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* rows, int32_t nrows,
-                                                  const int64_t* a_beg, const int64_t* c_rp,
+                                                  const int64_t* a_beg, OutRows c_rp,
                                                   int32_t* c_col, void* c_val) {
     typedef Sr<SR> S;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -43,7 +54,7 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
     const int64_t k = A.col[p];
     const typename S::acc_t a = S::load(A.val, p);
     const int64_t bs = B.rp[k], be = B.rp[k + 1];
-    const int64_t off = c_rp[i] - bs;
+    const int64_t off = c_rp.off(i) - bs;
     for (int64_t q = bs + lane_id(); q < be; q += SPG_WAVE) {
         c_col[off + q] = B.col[q];
         if (c_val) S::store(c_val, off + q, S::mul(a, S::load(B.val, q)));
@@ -54,7 +65,7 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
 template <int SR>
 __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
                                                    const int64_t* a_beg, const int64_t* a_end,
-                                                   const int64_t* c_rp, int32_t* c_col, void* c_val,
+                                                   OutRows c_rp, int32_t* c_col, void* c_val,
                                                    int64_t* cnt_out) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
@@ -89,7 +100,7 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
     }
     const uint64_t heads = __ballot(head);
     if (head) {
-        const int64_t o = c_rp[i] + lanes_below(heads);
+        const int64_t o = c_rp.off(i) + lanes_below(heads);
         c_col[o] = (int32_t)col;
         if (c_val) S::store(c_val, o, acc);
     }
@@ -97,12 +108,12 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
 }
 
 // cnt_out (optional) receives each row's output count; a count above the
-// slot c_rp[i+1]-c_rp[i] means the slot overflowed (only then is the output
+// slot c_rp.count(i) means the slot overflowed (only then is the output
 // incomplete).
 template <int SR, int NT, int LOG2T>
 __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* rows,
                                                  const int64_t* a_beg, const int64_t* a_end,
-                                                 const int64_t* c_rp, int32_t* c_col, void* c_val,
+                                                 OutRows c_rp, int32_t* c_col, void* c_val,
                                                  int64_t* cnt_out) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
@@ -164,8 +175,8 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     __syncthreads();  // every slot is in registers before the table is reused
     int32_t cnt;
     int32_t pos = block_exclusive_scan<NT, int32_t>(mine, &cnt, red);
-    const int64_t o = c_rp[i];
-    const int32_t cnt_sym = (int32_t)(c_rp[i + 1] - o);
+    const int64_t o = c_rp.off(i);
+    const int32_t cnt_sym = (int32_t)c_rp.count(i);
     if (cnt_out && threadIdx.x == 0) cnt_out[i] = cnt;
     if (cnt_out && cnt > cnt_sym) return;  // slot overflow: the row is redone exactly
     // Output order.  When the row's columns span few enough bitmap words, the
@@ -320,7 +331,7 @@ template <int SR, int NT, int W, int GM>
 __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* rows, int64_t nrows,
                                                   const int64_t* a_beg, const int64_t* a_end,
                                                   const int32_t* split, int32_t P,
-                                                  const int64_t* c_rp, int32_t* c_col, void* c_val) {
+                                                  OutRows c_rp, int32_t* c_col, void* c_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
     constexpr int NWD = W / 32;
@@ -338,8 +349,8 @@ __global__ void __launch_bounds__(NT) k_num_dense(Csr A, Csr B, const int32_t* r
     for (int64_t item = blockIdx.x; item < nrows; item += gridDim.x) {
     const int64_t i = rows[item];
     const int64_t beg = a_beg[i], end = a_end[i];
-    int64_t off = c_rp[i];
-    const int64_t row_end = c_rp[i + 1];
+    int64_t off = c_rp.off(i);
+    const int64_t row_end = off + c_rp.count(i);
     const int c_first = 0, c_last = P;
     // Rows with at most NT entries in the window keep their A entry (column
     // k, start of B(k,:), position reached in B(k,:)) in registers across
@@ -479,7 +490,7 @@ template <int SR, int NT, int GM>
 __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* rows,
                                                  const int64_t* a_beg, const int64_t* a_end,
                                                  const uint32_t* bm_save, const int32_t* heavy_idx,
-                                                 int32_t nwords, const int64_t* c_rp, int32_t* c_col,
+                                                 int32_t nwords, OutRows c_rp, int32_t* c_col,
                                                  void* c_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
@@ -490,8 +501,8 @@ __global__ void __launch_bounds__(NT) k_num_rank(Csr A, Csr B, const int32_t* ro
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
     const int64_t i = rows[blockIdx.x];
-    const int64_t off = c_rp[i];
-    const int32_t cnt = (int32_t)(c_rp[i + 1] - off);
+    const int64_t off = c_rp.off(i);
+    const int32_t cnt = (int32_t)c_rp.count(i);
     const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords;
     stage_bitmap_words<NT>(src, nwords, bw);
     __syncthreads();
@@ -570,7 +581,7 @@ __global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const
                                                   const int64_t* a_end, const uint32_t* bm_save,
                                                   const int32_t* heavy_idx, int32_t nwords, const int32_t* split,
                                                   int32_t P, const RankItem* items, const int32_t* nitems,
-                                                  int32_t RC, int32_t G, const int64_t* c_rp, int32_t* c_col,
+                                                  int32_t RC, int32_t G, OutRows c_rp, int32_t* c_col,
                                                   void* c_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
@@ -589,7 +600,7 @@ __global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const
         const int64_t i = rows[item.r];
         const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords + (int64_t)item.c0 * WPC;
         const int nw = (item.c1 - item.c0) * WPC;
-        const int64_t off = c_rp[i] + item.roff;
+        const int64_t off = c_rp.off(i) + item.roff;
         const int32_t cbase = item.c0 * W;
         // packed words and columns
         stage_bitmap_words<NT>(src, nw, bw);

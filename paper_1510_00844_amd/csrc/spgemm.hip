@@ -106,6 +106,7 @@ struct spg_plan_s {
     DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
     DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save, rank_items;
     DevBuf lpt_hist, lpt_tmp;  // ordering of heavy bins by work
+    const int64_t* out_pos = nullptr;  // numeric output offsets per row (set while a sub-product writes into a full one)
     int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
     LayerDesc* h_layers = nullptr; // pinned staging for merge descriptors
     int h_layers_cap = 0;
@@ -123,7 +124,8 @@ struct spg_plan_s {
     int dense_chunks = 0;
 
     // single-pass (predicted sizes) state
-    DevBuf lcap, lcnt, slot, pcol, pval, fb_list, fb_redo, sub_rp, sub_col, sub_val, sub_crp, sub_ccol, sub_cval, mlp_tmp;
+    DevBuf lcap, lcnt, slot, pcol, pval, fb_list, fb_redo, sub_rp, sub_col, sub_val, sub_crp, mlp_tmp;
+    DevBuf sub_pos;  // final output offsets of the recomputed rows
     spg_plan sub = nullptr;  // plan of the exact method for the rows it must redo
     Signature lsig;
     bool have_learned = false;
@@ -491,7 +493,7 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
                       &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save, &P->rank_items,
                       &P->lpt_hist, &P->lpt_tmp,
                       &P->lcap, &P->lcnt, &P->slot, &P->pcol, &P->pval, &P->fb_list, &P->fb_redo, &P->sub_rp,
-                      &P->sub_col, &P->sub_val, &P->sub_crp, &P->sub_ccol, &P->sub_cval, &P->mlp_tmp,
+                      &P->sub_col, &P->sub_val, &P->sub_crp, &P->mlp_tmp, &P->sub_pos,
                       &P->mis_key, &P->mis_m1, &P->mis_cand, &P->mis_new, &P->mis_a1, &P->mis_flags, &P->mis_agg1,
                       &P->mis_ctr})
         b->release();
@@ -852,7 +854,7 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
 // ---------------------------------------------------------------------------
 template <int SR, int NT, int LOG2T>
 static spg_status launch_num_hash(spg_plan P, Csr A, Csr B, const int32_t* rows, int64_t nr,
-                                  const int64_t* crp, int32_t* ccol, void* cval, int64_t* cnt_out) {
+                                  OutRows crp, int32_t* ccol, void* cval, int64_t* cnt_out) {
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
     return launch(P, "num_hash" + std::to_string(1 << LOG2T), [&] {
@@ -862,7 +864,7 @@ static spg_status launch_num_hash(spg_plan P, Csr A, Csr B, const int32_t* rows,
 
 template <int SR>
 static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int32_t* rows, int64_t nr,
-                                    const int64_t* crp, int32_t* ccol, void* cval, int64_t* cnt_out = nullptr) {
+                                    OutRows crp, int32_t* ccol, void* cval, int64_t* cnt_out = nullptr) {
     switch (lg) {
         case 7: return launch_num_hash<SR, 64, 7>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
         case 8: return launch_num_hash<SR, 64, 8>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
@@ -876,7 +878,9 @@ static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int3
 }
 
 template <int SR>
-static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* crp, int32_t* ccol, void* cval) {
+static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr, int32_t* ccol, void* cval) {
+    // output rows start at c_row_ptr, or at P->out_pos for a gathered sub-product
+    const OutRows crp(c_row_ptr, P->out_pos);
     const int32_t* lists = P->lists.as<int32_t>();
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
@@ -1550,19 +1554,21 @@ static spg_status learned_fetch_sr(spg_plan P, const spg_csr* A, const spg_csr* 
         }));
     }
     if (P->l_nfb > 0) {
-        const size_t w = SR == SR_BOOL ? 1 : 8;
-        SPG_TRY(P->sub_ccol.ensure(4 * (size_t)std::max<int64_t>(P->l_sub_nnz, 1), "recomputed output"));
-        SPG_TRY(P->sub_cval.ensure(w * (size_t)std::max<int64_t>(P->l_sub_nnz, 1), "recomputed output"));
-        spg_csr S = sub_matrix(P, A);
-        SPG_TRY(spgemm_numeric(P->sub, P->l_sr, &S, B, P->lsig.k_lo, P->lsig.k_hi, P->sub_crp.as<int64_t>(),
-                               P->sub_ccol.as<int32_t>(), c_val ? P->sub_cval.p : nullptr));
-        P->cur = nullptr;
-        SPG_TRY(launch(P, "copy_rows", [&] {
-            k_copy_rows<SR><<<(unsigned)std::min<int64_t>(P->l_nfb, 65536), 256, 0, cs(P)>>>(P->l_nfb, P->fb_list.as<int32_t>(), nullptr,
-                                                                       P->sub_crp.as<int64_t>(), c_row_ptr,
-                                                                       P->sub_ccol.as<int32_t>(), P->sub_cval.p, c_col,
-                                                                       c_val);
+        // the recomputed rows write straight into the caller's arrays: the
+        // sub-product's numeric pass takes their final offsets
+        SPG_TRY(P->sub_pos.ensure(8 * (size_t)P->l_nfb, "recomputed rows"));
+        int64_t* pos = P->sub_pos.as<int64_t>();
+        SPG_TRY(launch(P, "gather_offsets", [&] {
+            k_gather_offsets<<<grid_for(P->l_nfb, 256), 256, 0, cs(P)>>>(P->fb_list.as<int32_t>(), (int32_t)P->l_nfb,
+                                                                         c_row_ptr, pos);
         }));
+        spg_csr S = sub_matrix(P, A);
+        P->sub->out_pos = pos;
+        const spg_status st = spgemm_numeric(P->sub, P->l_sr, &S, B, P->lsig.k_lo, P->lsig.k_hi,
+                                             P->sub_crp.as<int64_t>(), c_col, c_val);
+        P->sub->out_pos = nullptr;
+        SPG_TRY(st);
+        P->cur = nullptr;
     }
     return SPG_OK;
 }
