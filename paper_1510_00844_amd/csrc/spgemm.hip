@@ -1314,10 +1314,15 @@ extern "C" spg_status spg_row_training_data(spg_plan P, const int64_t* c_row_ptr
 // ---------------------------------------------------------------------------
 // single-pass product with predicted sizes
 // ---------------------------------------------------------------------------
+// Largest capacity (log2) of the fused single-pass kernel: what the LDS
+// allows, and no more than rank_max_nnz (larger rows take the exact path,
+// where column-chunk items keep more workgroups on a CU).
 static int fused_max_log2(spg_plan P, int64_t n) {
     const int64_t nwords = (n + 31) / 32;
     if (nwords > 8 * 512) return 0;  // the fused kernel keeps <= 8 bitmap words per thread
-    for (int lg = 14; lg >= RANK_MIN_LOG2; --lg)
+    int top = 14;
+    while (top >= RANK_MIN_LOG2 && (1ll << top) > P->opts.rank_max_nnz) --top;
+    for (int lg = top; lg >= RANK_MIN_LOG2; --lg)
         if (nwords * 8 + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) return lg;
     return 0;
 }
@@ -1334,6 +1339,8 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
     int64_t bin_off[NBINS + 1];
     bin_off[0] = 0;
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->l_counts[x];
+    // the fused bitmap-rank rows (bins 13..15), heaviest first
+    if (bin_off[NBINS] - bin_off[BIN_DENSE_PAR] > 1) SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, bin_off));
     SPG_TRY(fork_streams(P));
     const std::vector<int> order = bins_by_work(P->l_counts, P->l_counts + NBINS);
     StreamLoad lload(P, P->l_counts);
