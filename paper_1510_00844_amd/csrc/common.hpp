@@ -77,17 +77,76 @@ template <> struct Sr<SR_BOOL> {
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }
 
+// Value of lane (lane ^ j), j a power of two known after unrolling.  Within
+// 16 lanes the data moves by DPP (a VALU operand modifier, no LDS round
+// trip): quad permutes for j = 1, 2; the two row shifts by 4 for j = 4;
+// the row rotation by 8 for j = 8.  ds_swizzle (xor mode, within 32 lanes)
+// serves j = 16 and ds_bpermute j = 32.
+template <int CTRL>
+__device__ inline int dpp_mov(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+__device__ inline uint32_t lane_xor_u32(uint32_t v, int j) {
+    const int x = (int)v;
+    switch (j) {
+        case 1: return (uint32_t)dpp_mov<0xB1>(x);  // quad_perm [1,0,3,2]
+        case 2: return (uint32_t)dpp_mov<0x4E>(x);  // quad_perm [2,3,0,1]
+        case 4: {
+            const int up = dpp_mov<0x104>(x);  // row_shl:4, lane i reads i + 4
+            const int dn = dpp_mov<0x114>(x);  // row_shr:4, lane i reads i - 4
+            return (uint32_t)((lane_id() & 4) ? dn : up);
+        }
+        case 8: return (uint32_t)dpp_mov<0x128>(x);  // row_ror:8
+        case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);  // and 0x1f, xor 0x10
+        default: return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ j) << 2, x);
+    }
+}
 template <typename T>
-__device__ inline T wave_inclusive_scan_add(T v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < SPG_WAVE; d <<= 1) {
-        T o = __shfl_up(v, d, SPG_WAVE);
-        if (lane >= d) v += o;
+__device__ inline T lane_xor(T v, int j) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 4) {
+        uint32_t u;
+        __builtin_memcpy(&u, &v, 4);
+        u = lane_xor_u32(u, j);
+        __builtin_memcpy(&v, &u, 4);
+    } else {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        const uint32_t lo = lane_xor_u32((uint32_t)u, j), hi = lane_xor_u32((uint32_t)(u >> 32), j);
+        u = ((uint64_t)hi << 32) | lo;
+        __builtin_memcpy(&v, &u, 8);
     }
     return v;
 }
 
+// Inclusive prefix sum over the wave.  32-bit integers: Hillis-Steele
+// within each row of 16 lanes by DPP row shifts (out-of-row sources read
+// 0), then each row's total is broadcast to the rows above (row_bcast:15
+// into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+template <typename T>
+__device__ inline T wave_inclusive_scan_add(T v) {
+    if constexpr (sizeof(T) == 4 && __is_integral(T)) {
+        int x = (int)v;
+        x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
+        x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);  // row_shr:2
+        x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);  // row_shr:4
+        x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);  // row_shr:8
+        x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+        x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+        return (T)x;
+    } else {
+        const int lane = lane_id();
+#pragma unroll
+        for (int d = 1; d < SPG_WAVE; d <<= 1) {
+            T o = __shfl_up(v, d, SPG_WAVE);
+            if (lane >= d) v += o;
+        }
+        return v;
+    }
+}
+
+// (The reductions keep ds_bpermute: with DPP steps the bitmap kernel's
+// per-chunk count loop ran 1.7x longer on 524288-column rows, measured.)
 template <typename T>
 __device__ inline T wave_reduce_add(T v) {
 #pragma unroll
@@ -150,8 +209,8 @@ __device__ inline void block_min_max(T& mn, T& mx, T* tmp) {
     constexpr int NW = NT / SPG_WAVE;
 #pragma unroll
     for (int d = SPG_WAVE / 2; d > 0; d >>= 1) {
-        T a = __shfl_xor(mn, d, SPG_WAVE);
-        T b = __shfl_xor(mx, d, SPG_WAVE);
+        T a = lane_xor(mn, d);
+        T b = lane_xor(mx, d);
         mn = a < mn ? a : mn;
         mx = b > mx ? b : mx;
     }
@@ -209,7 +268,7 @@ __device__ inline uint64_t wave_bitonic_sort_u64(uint64_t key) {
     for (int k = 2; k <= SPG_WAVE; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            uint64_t o = __shfl_xor(key, j, SPG_WAVE);
+            uint64_t o = lane_xor(key, j);
             bool lower = (lane & j) == 0;
             bool up = (lane & k) == 0;
             // lower lane keeps min when ascending, max when descending
