@@ -119,6 +119,31 @@ __device__ inline T lane_xor(T v, int j) {
     return v;
 }
 
+// Value of lane i + 1 (DPP wave_shl:1) and of lane i - 1 (wave_shr:1).  The
+// end lanes (63, resp. 0) receive an unspecified value: callers exclude them.
+template <int CTRL, typename T>
+__device__ inline T lane_shift(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 4) {
+        int u;
+        __builtin_memcpy(&u, &v, 4);
+        u = dpp_mov<CTRL>(u);
+        __builtin_memcpy(&v, &u, 4);
+    } else {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        const uint32_t lo = (uint32_t)dpp_mov<CTRL>((int)(uint32_t)u);
+        const uint32_t hi = (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(u >> 32));
+        u = ((uint64_t)hi << 32) | lo;
+        __builtin_memcpy(&v, &u, 8);
+    }
+    return v;
+}
+template <typename T>
+__device__ inline T lane_next(T v) { return lane_shift<0x130>(v); }
+template <typename T>
+__device__ inline T lane_prev(T v) { return lane_shift<0x138>(v); }
+
 // Inclusive prefix sum over the wave.  32-bit integers: Hillis-Steele
 // within each row of 16 lanes by DPP row shifts (out-of-row sources read
 // 0), then each row's total is broadcast to the rows above (row_bcast:15

@@ -85,17 +85,21 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
     const bool valid = key != ~0ull;
     v = __shfl(v, (int)(key & 63), SPG_WAVE);  // value travels with its key
     const uint64_t col = key >> 6;
-    const uint64_t prev = __shfl_up(col, 1, SPG_WAVE);
+    const uint64_t prev = lane_prev(col);
     const bool head = valid && (lane == 0 || prev != col);
-    // fold the run that starts at each head, left to right
+    // fold the run that starts at each head, left to right: at step s every
+    // lane holds the entry s lanes above it (shifted one lane per step)
     V acc = v;
     bool open = head;
+    uint64_t ncol = col;
+    V nv = v;
+    int nvalid = valid ? 1 : 0;
     for (int s = 1; s < SPG_WAVE; ++s) {
         if (!__any(open)) break;
-        uint64_t ncol = __shfl_down(col, s, SPG_WAVE);
-        V nv = __shfl_down(v, s, SPG_WAVE);
-        bool nvalid = __shfl_down((int)valid, s, SPG_WAVE) != 0;
-        open = open && (lane + s < SPG_WAVE) && nvalid && ncol == col;
+        ncol = lane_next(ncol);
+        nv = lane_next(nv);
+        nvalid = lane_next(nvalid);
+        open = open && (lane + s < SPG_WAVE) && nvalid != 0 && ncol == col;
         if (open) acc = S::add(acc, nv);
     }
     const uint64_t heads = __ballot(head);

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, const int32_t* 
     bool have = wave_locate_product(A, B, a_beg[i], a_end[i], p, q);
     uint64_t key = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
     key = wave_bitonic_sort_u64(key);
-    uint64_t prev = __shfl_up(key, 1, SPG_WAVE);
+    uint64_t prev = lane_prev(key);
     const int lane = lane_id();
     bool head = key != ~0ull && (lane == 0 || prev != key);
     uint64_t heads = __ballot(head);
