@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
     }
 }
 
-// cnt_out (optional) receives each row's output count.
+// cnt_out (optional) receives each row's output count.  4 waves per block,
+// SMALL_ROWS rows per wave (their loads in flight together).
 template <int SR>
 __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
                                                    const int64_t* a_beg, const int64_t* a_end,
@@ -69,46 +70,54 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
                                                    int64_t* cnt_out) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= nrows) return;
-    const int64_t i = rows[r];
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w * SMALL_ROWS >= nrows) return;  // whole wave leaves; no block barriers below
     const int lane = lane_id();
-    int64_t p = 0, q = 0;
-    bool have = wave_locate_product(A, B, a_beg[i], a_end[i], p, q);
-    V v = S::zero();
-    uint64_t key = ~0ull;
-    if (have) {
-        v = S::mul(S::load(A.val, p), S::load(B.val, q));
-        key = ((uint64_t)(uint32_t)B.col[q] << 6) | (uint64_t)lane;  // (column, product order)
+    V vals[SMALL_ROWS];
+    uint64_t keys[SMALL_ROWS];
+    int64_t row[SMALL_ROWS];
+    for_small_rows(A, B, rows, nrows, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t p, int64_t q) {
+        row[u] = i;
+        vals[u] = S::zero();
+        keys[u] = ~0ull;
+        if (have) {
+            vals[u] = S::mul(S::load(A.val, p), S::load(B.val, q));
+            keys[u] = ((uint64_t)(uint32_t)B.col[q] << 6) | (uint64_t)lane;  // (column, product order)
+        }
+    });
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        if (w * SMALL_ROWS + u >= nrows) break;
+        const int64_t i = row[u];
+        const uint64_t key = wave_bitonic_sort_u64(keys[u]);
+        const bool valid = key != ~0ull;
+        const V v = __shfl(vals[u], (int)(key & 63), SPG_WAVE);  // value travels with its key
+        const uint64_t col = key >> 6;
+        const uint64_t prev = lane_prev(col);
+        const bool head = valid && (lane == 0 || prev != col);
+        // fold the run that starts at each head, left to right: at step s
+        // every lane holds the entry s lanes above it (shifted one lane per step)
+        V acc = v;
+        bool open = head;
+        uint64_t ncol = col;
+        V nv = v;
+        int nvalid = valid ? 1 : 0;
+        for (int s = 1; s < SPG_WAVE; ++s) {
+            if (!__any(open)) break;
+            ncol = lane_next(ncol);
+            nv = lane_next(nv);
+            nvalid = lane_next(nvalid);
+            open = open && (lane + s < SPG_WAVE) && nvalid != 0 && ncol == col;
+            if (open) acc = S::add(acc, nv);
+        }
+        const uint64_t heads = __ballot(head);
+        if (head) {
+            const int64_t o = c_rp.off(i) + lanes_below(heads);
+            c_col[o] = (int32_t)col;
+            if (c_val) S::store(c_val, o, acc);
+        }
+        if (cnt_out && lane == 0) cnt_out[i] = __popcll(heads);
     }
-    key = wave_bitonic_sort_u64(key);
-    const bool valid = key != ~0ull;
-    v = __shfl(v, (int)(key & 63), SPG_WAVE);  // value travels with its key
-    const uint64_t col = key >> 6;
-    const uint64_t prev = lane_prev(col);
-    const bool head = valid && (lane == 0 || prev != col);
-    // fold the run that starts at each head, left to right: at step s every
-    // lane holds the entry s lanes above it (shifted one lane per step)
-    V acc = v;
-    bool open = head;
-    uint64_t ncol = col;
-    V nv = v;
-    int nvalid = valid ? 1 : 0;
-    for (int s = 1; s < SPG_WAVE; ++s) {
-        if (!__any(open)) break;
-        ncol = lane_next(ncol);
-        nv = lane_next(nv);
-        nvalid = lane_next(nvalid);
-        open = open && (lane + s < SPG_WAVE) && nvalid != 0 && ncol == col;
-        if (open) acc = S::add(acc, nv);
-    }
-    const uint64_t heads = __ballot(head);
-    if (head) {
-        const int64_t o = c_rp.off(i) + lanes_below(heads);
-        c_col[o] = (int32_t)col;
-        if (c_val) S::store(c_val, o, acc);
-    }
-    if (cnt_out && lane == 0) cnt_out[i] = __popcll(heads);
 }
 
 // cnt_out (optional) receives each row's output count; a count above the

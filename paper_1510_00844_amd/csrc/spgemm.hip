@@ -776,7 +776,7 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
         use_stream(P, sload, (int)oi, P->sym_counts, bb);
         if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "sym_small", [&] {
-                k_sym_small<<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
+                k_sym_small<<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
                                                                      P->a_end.as<int64_t>(), cnt);
             }));
         } else if (bb == BIN_DENSE) {
@@ -921,7 +921,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
             }));
         } else if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "num_small", [&] {
-                k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
+                k_num_small<SR><<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
             }));
         } else if (bb >= BIN_RANK0) {
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
@@ -1356,7 +1356,7 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
             }));
         } else if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "num_small", [&] {
-                k_num_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, slot, pcol, pval,
+                k_num_small<SR><<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, slot, pcol, pval,
                                                                      cnt);
             }));
         } else if (bb >= BIN_RANK0) {

@@ -60,22 +60,110 @@ __device__ inline bool wave_locate_product(const Csr& A, const Csr& B, int64_t b
     return have;
 }
 
-// 4 waves per block, one row per wave.
-__global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
-                                                   const int64_t* a_beg, const int64_t* a_end,
-                                                   int64_t* cnt) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= nrows) return;  // whole wave leaves; no block barriers below
-    const int64_t i = rows[r];
-    int64_t p = 0, q = 0;
-    bool have = wave_locate_product(A, B, a_beg[i], a_end[i], p, q);
-    uint64_t key = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
-    key = wave_bitonic_sort_u64(key);
-    uint64_t prev = lane_prev(key);
+// The same for SMALL_ROWS rows at once whose A windows hold at most 64
+// entries (one group): each dependent load level (A columns, B extents, B
+// entries) is issued for all rows before any is waited for, so a wave keeps
+// that many rows' loads in flight.  Lane f takes product f of row u.
+constexpr int SMALL_ROWS = 2;
+__device__ inline void wave_locate_rows(const Csr& A, const Csr& B, const int64_t* beg, const int64_t* end,
+                                        bool* have, int64_t* p_out, int64_t* q_out) {
     const int lane = lane_id();
-    bool head = key != ~0ull && (lane == 0 || prev != key);
-    uint64_t heads = __ballot(head);
-    if (lane == 0) cnt[i] = __popcll(heads);
+    int64_t kk[SMALL_ROWS];
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        const int64_t p = beg[u] + lane;
+        kk[u] = p < end[u] ? (int64_t)A.col[p] : -1;
+    }
+    int64_t bs[SMALL_ROWS];
+    int len[SMALL_ROWS];
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        bs[u] = 0;
+        len[u] = 0;
+        if (kk[u] >= 0) {
+            bs[u] = B.rp[kk[u]];
+            len[u] = (int)(B.rp[kk[u] + 1] - bs[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        const int incl = wave_inclusive_scan_add(len[u]);
+        const int total = __builtin_amdgcn_readlane(incl, SPG_WAVE - 1);
+        int t = 0;  // first lane whose inclusive count exceeds this lane's product
+#pragma unroll
+        for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
+            const int v = __shfl(incl, t + step - 1, SPG_WAVE);
+            if (v <= lane) t += step;
+        }
+        t = t < SPG_WAVE ? t : SPG_WAVE - 1;
+        const int64_t bst = __shfl(bs[u], t, SPG_WAVE);
+        const int excl = __shfl(incl - len[u], t, SPG_WAVE);
+        have[u] = lane < total;
+        p_out[u] = beg[u] + t;
+        q_out[u] = bst + (lane - excl);
+    }
+}
+
+// The rows of one wave: SMALL_ROWS consecutive list entries.  locate(u, i,
+// have, p, q) gets each row's products; rows past the list are skipped, and a
+// row with more than 64 A entries in the window (empty B rows among them)
+// falls back to the one-row search.
+template <class Body>
+__device__ inline void for_small_rows(const Csr& A, const Csr& B, const int32_t* rows, int32_t nrows,
+                                      const int64_t* a_beg, const int64_t* a_end, Body body) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t i[SMALL_ROWS], beg[SMALL_ROWS], end[SMALL_ROWS];
+    bool ok[SMALL_ROWS];
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        const int64_t r = w * SMALL_ROWS + u;
+        ok[u] = r < nrows;
+        i[u] = ok[u] ? rows[r] : 0;
+    }
+    bool one_group = true;
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        beg[u] = ok[u] ? a_beg[i[u]] : 0;
+        end[u] = ok[u] ? a_end[i[u]] : 0;
+        one_group = one_group && end[u] - beg[u] <= SPG_WAVE;
+    }
+    bool have[SMALL_ROWS];
+    int64_t p[SMALL_ROWS], q[SMALL_ROWS];
+    if (one_group) {
+        wave_locate_rows(A, B, beg, end, have, p, q);
+    } else {
+#pragma unroll
+        for (int u = 0; u < SMALL_ROWS; ++u) {
+            p[u] = q[u] = 0;
+            have[u] = wave_locate_product(A, B, beg[u], end[u], p[u], q[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u)
+        if (ok[u]) body(u, i[u], have[u], p[u], q[u]);
+}
+
+// 4 waves per block, SMALL_ROWS rows per wave.
+__global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
+                                                   const int64_t* a_beg, const int64_t* a_end, int64_t* cnt) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w * SMALL_ROWS >= nrows) return;  // whole wave leaves; no block barriers below
+    const int lane = lane_id();
+    uint64_t keys[SMALL_ROWS];
+    int64_t row[SMALL_ROWS];
+    for_small_rows(A, B, rows, nrows, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t, int64_t q) {
+        keys[u] = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
+        row[u] = i;
+    });
+#pragma unroll
+    for (int u = 0; u < SMALL_ROWS; ++u) {
+        if (w * SMALL_ROWS + u >= nrows) break;
+        const uint64_t key = wave_bitonic_sort_u64(keys[u]);
+        const uint64_t prev = lane_prev(key);
+        const bool head = key != ~0ull && (lane == 0 || prev != key);
+        const uint64_t heads = __ballot(head);
+        if (lane == 0) cnt[row[u]] = __popcll(heads);
+    }
 }
 
 template <int NT, int LOG2T>
