@@ -59,7 +59,8 @@ __device__ inline int find_sorted(const int64_t* off, int32_t nb, int64_t x) {
 }
 
 __global__ void __launch_bounds__(256) k_batch_assemble(const BatchDesc* d, int32_t nb, int64_t rows, int64_t nnz,
-                                                        int32_t vw, int64_t* rp, int32_t* col, void* val) {
+                                                        int32_t vw, int32_t structure, int64_t* rp, int32_t* col,
+                                                        void* val) {
     __shared__ int64_t s_row[BATCH_LDS_MAX], s_nz[BATCH_LDS_MAX];
     const bool lds = nb <= BATCH_LDS_MAX;
     if (lds)
@@ -68,20 +69,29 @@ __global__ void __launch_bounds__(256) k_batch_assemble(const BatchDesc* d, int3
             s_nz[b] = d[b].nz_off;
         }
     __syncthreads();
-    const int64_t n = rows + 1 > nnz ? rows + 1 : nnz;
-    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256) {
-        if (x < rows) {
+    // structure = 0: the row pointers and columns are in place from an
+    // earlier call with the same instances; only the values are copied
+    const int64_t n = structure ? (rows + 1 > nnz ? rows + 1 : nnz) : nnz;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t x = base + threadIdx.x;
+        if (structure && x < rows) {
             const BatchDesc& D = d[lds ? find_sorted(s_row, nb, x) : find_instance(d, nb, x)];
             rp[x] = D.nz_off + (D.rp[x - D.row_off] - D.rp[0]);
-        } else if (x == rows) {
+        } else if (structure && x == rows) {
             rp[rows] = nnz;
         }
-        if (x < nnz) {
-            const BatchDesc& D = d[lds ? find_sorted(s_nz, nb, x) : find_instance_nz(d, nb, x)];
-            const int64_t e = x - D.nz_off + D.rp[0];
-            col[x] = (int32_t)(D.col[e] + D.col_off);
-            if (vw == 8) ((uint64_t*)val)[x] = ((const uint64_t*)D.val)[e];
-            else if (vw == 1) ((uint8_t*)val)[x] = D.val ? ((const uint8_t*)D.val)[e] : (uint8_t)1;
+        if (base < nnz) {
+            // the instance of the block's first entry (one search, the same
+            // address for every thread), then forward to this thread's entry
+            int b = lds ? find_sorted(s_nz, nb, base) : find_instance_nz(d, nb, base);
+            while (b + 1 < nb && (lds ? s_nz[b + 1] : d[b + 1].nz_off) <= x) ++b;
+            if (x < nnz) {
+                const BatchDesc& D = d[b];
+                const int64_t e = x - D.nz_off + D.rp[0];
+                if (structure) col[x] = (int32_t)(D.col[e] + D.col_off);
+                if (vw == 8) ((uint64_t*)val)[x] = ((const uint64_t*)D.val)[e];
+                else if (vw == 1) ((uint8_t*)val)[x] = D.val ? ((const uint8_t*)D.val)[e] : (uint8_t)1;
+            }
         }
     }
 }

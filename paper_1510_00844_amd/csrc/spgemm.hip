@@ -1644,20 +1644,22 @@ static spg_status galerkin_sequence(spg_plan P, GalerkinState* G, bool eager) {
     const int32_t vw = G->sr == SPG_SR_OR_AND_BOOL ? 1 : 8;
     P->cur = G->gs;
     // the assembled operands are canonical when the instances are; only the
-    // eager call may synchronize
+    // eager call may synchronize.  Later calls (replays) copy values only:
+    // the structure may not change between them, so the eager call's
+    // assembled row pointers and columns stay valid
     G->p1->opts.validate = G->p2->opts.validate = eager ? P->opts.validate : 0;
     SPG_TRY(launch(P, "batch_assemble", [&] {
-        k_batch_assemble<<<assemble_grid(G->rows_rt, G->nnz_rt), 256, 0, cs(P)>>>(d, nb, G->rows_rt, G->nnz_rt, vw,
+        k_batch_assemble<<<assemble_grid(G->rows_rt, G->nnz_rt), 256, 0, cs(P)>>>(d, nb, G->rows_rt, G->nnz_rt, vw, eager ? 1 : 0,
                                                                           G->rt_rp.as<int64_t>(), G->rt_col.as<int32_t>(),
                                                                           G->rt_val.p);
     }));
     SPG_TRY(launch(P, "batch_assemble", [&] {
-        k_batch_assemble<<<assemble_grid(G->rows_a, G->nnz_a), 256, 0, cs(P)>>>(d + nb, nb, G->rows_a, G->nnz_a, vw,
+        k_batch_assemble<<<assemble_grid(G->rows_a, G->nnz_a), 256, 0, cs(P)>>>(d + nb, nb, G->rows_a, G->nnz_a, vw, eager ? 1 : 0,
                                                                          G->a_rp.as<int64_t>(), G->a_col.as<int32_t>(),
                                                                          G->a_val.p);
     }));
     SPG_TRY(launch(P, "batch_assemble", [&] {
-        k_batch_assemble<<<assemble_grid(G->rows_r, G->nnz_r), 256, 0, cs(P)>>>(d + 2 * nb, nb, G->rows_r, G->nnz_r, vw,
+        k_batch_assemble<<<assemble_grid(G->rows_r, G->nnz_r), 256, 0, cs(P)>>>(d + 2 * nb, nb, G->rows_r, G->nnz_r, vw, eager ? 1 : 0,
                                                                          G->r_rp.as<int64_t>(), G->r_col.as<int32_t>(),
                                                                          G->r_val.p);
     }));
