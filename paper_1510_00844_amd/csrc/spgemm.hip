@@ -697,8 +697,8 @@ static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int3
     switch (lg) {
         case 7: return launch_sym_hash<64, 7>(P, A, B, rows, nr, cnt);
         case 8: return launch_sym_hash<64, 8>(P, A, B, rows, nr, cnt);
-        case 9: return launch_sym_hash<128, 9>(P, A, B, rows, nr, cnt);
-        case 10: return launch_sym_hash<256, 10>(P, A, B, rows, nr, cnt);
+        case 9: return launch_sym_hash<64, 9>(P, A, B, rows, nr, cnt);
+        case 10: return launch_sym_hash<128, 10>(P, A, B, rows, nr, cnt);
         case 11: return launch_sym_hash<256, 11>(P, A, B, rows, nr, cnt);
         case 12: return launch_sym_hash<512, 12>(P, A, B, rows, nr, cnt);
         case 13: return launch_sym_hash<512, 13>(P, A, B, rows, nr, cnt);
@@ -868,8 +868,8 @@ static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int3
     switch (lg) {
         case 7: return launch_num_hash<SR, 64, 7>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
         case 8: return launch_num_hash<SR, 64, 8>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
-        case 9: return launch_num_hash<SR, 128, 9>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
-        case 10: return launch_num_hash<SR, 256, 10>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 9: return launch_num_hash<SR, 64, 9>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
+        case 10: return launch_num_hash<SR, 128, 10>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
         case 11: return launch_num_hash<SR, 256, 11>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
         case 12: return launch_num_hash<SR, 256, 12>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
         case 13: return launch_num_hash<SR, 512, 13>(P, A, B, rows, nr, crp, ccol, cval, cnt_out);
