@@ -197,6 +197,10 @@ __device__ inline void for_each_product_u(int64_t a_beg, int64_t a_end, ProductL
             // product f of segment ta is B entry ta_rel + f; ta ends at ta_end
             int64_t ta_rel = readlane_i64(L.bstart[ta] - L.off[ta], 0);
             int32_t ta_end = __builtin_amdgcn_readfirstlane(L.off[ta + 1]);
+            // The step search is written out twice, inline here and as the
+            // locate lambda of the double-buffered form: folding this loop
+            // onto the lambda cost the rank kernels 4 to 11 more VGPRs (one
+            // workgroup fewer per CU), measured.
             if constexpr (!DB) {
                 for (int32_t fb = f0; fb < f1; fb += SPG_WAVE * U) {
                     int64_t qq[U];
