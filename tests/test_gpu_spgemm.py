@@ -141,6 +141,37 @@ def test_small_rows_exact_order(plan):
     assert C.val.tobytes() == ref.val.tobytes()
 
 
+def test_small_rows_with_many_empty_b_rows(plan):
+    """Rows of at most 64 products whose A windows hold more than 64 entries
+    (most point at empty B rows): the small-row kernels take two rows per
+    wave and fall back to the one-row search for such pairs; rows of every
+    kind are mixed so that both paths share waves.  FP64 bit-exact."""
+    rng = np.random.default_rng(47)
+    k, n, m = 400, 120, 97
+    # B: rows 0..39 hold 1-2 entries, the rest are empty
+    brows, bcols = [], []
+    for r in range(40):
+        for c in rng.choice(n, size=int(rng.integers(1, 3)), replace=False):
+            brows.append(r)
+            bcols.append(int(c))
+    B = synth.canonical_from_coo(k, n, np.array(brows), np.array(bcols), rng.random(len(brows)) + 0.5, dup="first")
+    arows, acols = [], []
+    for i in range(m):
+        if i % 3 == 0:  # > 64 entries, mostly empty B rows
+            cols = rng.choice(np.arange(40, k), size=80, replace=False).tolist() + rng.choice(40, size=3, replace=False).tolist()
+        else:
+            cols = rng.choice(k, size=int(rng.integers(1, 12)), replace=False).tolist()
+        arows += [i] * len(cols)
+        acols += cols
+    A = synth.canonical_from_coo(m, k, np.array(arows), np.array(acols), rng.random(len(arows)) + 0.5, dup="first")
+    f = oracle.row_flops(A, B)
+    assert f.max() <= 64 and np.diff(A.row_ptr).max() > 64
+    C = to_host(run(plan, "f64", A, B))
+    ref = oracle.spgemm(A, B, "f64")
+    assert_same_structure(C, ref)
+    assert C.val.tobytes() == ref.val.tobytes()
+
+
 @pytest.mark.parametrize("window", [(0, 0), (0, 1), (100, 1000), (4000, 8192), (8191, 8192), (0, 8192)])
 def test_inner_windows(plan, window):
     A = synth.rmat(13, 16, synth.G500, seed=43)
