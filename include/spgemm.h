@@ -102,7 +102,11 @@ typedef struct {
     int32_t gather_pipeline;   /* bitmap and rank-chunk kernels in the coalesced 4-step mode keep two
                                   rounds of gathers in flight (more registers, fewer waves): 0 = when
                                   the gathered B arrays exceed the 32 MiB of L2, 1 = never, 2 = always */
-    int32_t reserved[2];
+    int32_t fused_max_nnz;     /* learned single pass: rows predicted to hold at most this many outputs
+                                  (above the hash tables) may take the fused bitmap-and-rank kernel, up to
+                                  rank_max_nnz and what the LDS holds; 0 = never (default: on this GPU
+                                  the exact two-phase path is faster for such rows) */
+    int32_t reserved[1];
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;

@@ -48,7 +48,8 @@ class Opts(ctypes.Structure):
                 ("chunk_min_nnz", ctypes.c_int32), ("chunk_group", ctypes.c_int32),
                 ("rank_max_nnz", ctypes.c_int32), ("rank_block", ctypes.c_int32),
                 ("serial_heavy", ctypes.c_int32), ("chunk_unroll", ctypes.c_int32),
-                ("gather_pipeline", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("gather_pipeline", ctypes.c_int32), ("fused_max_nnz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -174,7 +175,7 @@ class Plan:
                  profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
                  dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0,
                  chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0, rank_block=0, serial_heavy=-1,
-                 chunk_unroll=0, gather_pipeline=0):
+                 chunk_unroll=0, gather_pipeline=0, fused_max_nnz=0):
         L = lib()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
@@ -189,7 +190,8 @@ class Plan:
                             ("sym_gather_map", sym_gather_map), ("sym_unroll", sym_unroll),
                             ("chunk_min_nnz", chunk_min_nnz), ("chunk_group", chunk_group),
                             ("rank_max_nnz", rank_max_nnz), ("rank_block", rank_block),
-                            ("chunk_unroll", chunk_unroll), ("gather_pipeline", gather_pipeline)):
+                            ("chunk_unroll", chunk_unroll), ("gather_pipeline", gather_pipeline),
+                            ("fused_max_nnz", fused_max_nnz)):
                 if v:
                     setattr(o, name, int(v))
             if serial_heavy >= 0:

@@ -419,6 +419,10 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         delete P;
         return fail(SPG_ERR_ARG, "hash_max_nnz must be in [1, 4096]");
     }
+    if (P->opts.fused_max_nnz < 0) {
+        delete P;
+        return fail(SPG_ERR_ARG, "fused_max_nnz must be >= 0");
+    }
     if (P->opts.gather_pipeline < 0 || P->opts.gather_pipeline > 2) {
         delete P;
         return fail(SPG_ERR_ARG, "gather_pipeline must be 0 (by size), 1 (off) or 2 (on)");
@@ -1315,13 +1319,15 @@ extern "C" spg_status spg_row_training_data(spg_plan P, const int64_t* c_row_ptr
 // single-pass product with predicted sizes
 // ---------------------------------------------------------------------------
 // Largest capacity (log2) of the fused single-pass kernel: what the LDS
-// allows, and no more than rank_max_nnz (larger rows take the exact path,
-// where column-chunk items keep more workgroups on a CU).
+// allows, and no more than fused_max_nnz and rank_max_nnz (larger rows take
+// the exact path, where column-chunk items keep more workgroups on a CU);
+// 0 = no fused kernel.
 static int fused_max_log2(spg_plan P, int64_t n) {
     const int64_t nwords = (n + 31) / 32;
     if (nwords > 8 * 512) return 0;  // the fused kernel keeps <= 8 bitmap words per thread
+    const int64_t lim = std::min<int64_t>(P->opts.rank_max_nnz, P->opts.fused_max_nnz);
     int top = 14;
-    while (top >= RANK_MIN_LOG2 && (1ll << top) > P->opts.rank_max_nnz) --top;
+    while (top >= RANK_MIN_LOG2 && (1ll << top) > lim) --top;
     for (int lg = top; lg >= RANK_MIN_LOG2; --lg)
         if (nwords * 8 + (8ll << lg) + RANK_STATIC_LDS <= P->max_lds) return lg;
     return 0;

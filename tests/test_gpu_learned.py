@@ -112,6 +112,23 @@ def test_single_pass_equals_two_phase_and_oracle(plan, sr):
     check_full_vs_oracle(C, A, A, sr)
 
 
+def test_fused_single_pass_equals_oracle():
+    """The fused bitmap-and-rank single pass (off by default), for rows
+    predicted above the hash tables."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    A = synth.rmat(13, 16, synth.G500, seed=44)
+    params = torch.tensor(mlp.init_params(2), dtype=torch.float32, device="cuda")
+    p = spg.Plan(fused_max_nnz=16384)
+    try:
+        C, st = _learned_vs_plain(p, A, "f64", params)
+        fused = sum(st["bin_rows"][b] for b in range(13, 16))
+        assert fused > 0, st
+        check_full_vs_oracle(C, A, A, "f64")
+    finally:
+        p.close()
+
+
 def test_forced_overflow_falls_back(plan):
     """A network that predicts 0 for every row sizes each slot at its lower
     bound max_k nnz(B(k,:)): nearly every predicted row overflows and is
@@ -142,17 +159,28 @@ def test_window_single_pass(plan):
         check_full_vs_oracle(C, A, B, "f64", lo, hi)
 
 
-def test_trained_predictor_gain(plan):
+def test_trained_predictor_gain():
     """The shipped trained weights against sizing without a predictor
     (capacity = min(flops, n)), on an R-MAT G500 scale-16 product (not in
-    the training set): the same result; with the predictor more of C is
-    produced in the single pass, fewer rows need the exact method, and the
-    padded slots are used far more fully."""
+    the training set), with the fused single pass on (rows up to 8192
+    predicted outputs), where the capacities depend on the prediction: the
+    same result; with the predictor more of C is produced in the single
+    pass, fewer rows need the exact method, and the padded slots are used
+    far more fully."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     from paper_1510_00844_amd import learned
     import os
     if not os.path.exists(learned.WEIGHTS):
         pytest.skip("no trained weights")
-    params = learned.load()
+    plan = spg.Plan(fused_max_nnz=8192)
+    try:
+        _predictor_gain(plan, learned.load())
+    finally:
+        plan.close()
+
+
+def _predictor_gain(plan, params):
     A = synth.rmat(16, 16, synth.G500, seed=2)
     dA = to_dev(A)
     nnz_l, st_l = spg.spgemm_learned_run(plan, "f64", dA, dA, params, 0.15)
