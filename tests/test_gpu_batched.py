@@ -150,6 +150,42 @@ def test_graph_replay_and_value_update(plan):
         assert np.array_equal(dense_got, dense_ref), b
 
 
+def _heavy_instance(n, agg, density, seed):
+    """Aggregation of `agg` fine points per coarse point over a random
+    operator dense enough that the rows of R^T A take the bitmap and rank
+    paths (the heavy bins the captured graph orders by work)."""
+    rng = np.random.default_rng(seed)
+    a = rng.random((n, n)) < density
+    r, c = np.nonzero(a)
+    A = synth.canonical_from_coo(n, n, r, c, rng.integers(-2, 3, r.size).astype(np.float64), dup="first")
+    m = (n + agg - 1) // agg
+    rows = np.arange(n)
+    R = synth.canonical_from_coo(n, m, rows, rows // agg, np.ones(n), dup="first")
+    RT = synth.canonical_from_coo(m, n, rows // agg, rows, np.ones(n), dup="first")
+    return RT, A, R
+
+
+def test_graph_replay_with_heavy_rows(plan):
+    """Instances whose products have heavy rows: the captured graph holds
+    the heavy bins' work ordering and the bitmap and rank kernels; replays
+    match the eager call and the oracle bit for bit (integer values)."""
+    inst = [_heavy_instance(512, 64, 0.2, 1), _heavy_instance(300, 50, 0.3, 2), _heavy_instance(640, 80, 0.15, 3)]
+    dev, res = _run(plan, inst, "f64", use_graph=True)
+    first = [to_host(C) for C in res.fetch(plan)]
+    for b, ((RT, A, R), h) in enumerate(zip(inst, first)):
+        ref = _oracle_galerkin(RT, A, R, "f64")
+        assert_same_structure(h, ref)
+        assert np.array_equal(h.val, ref.val), b
+    for rep in range(3):
+        torch.cuda.synchronize()
+        res2 = spg.spgemm_galerkin_batched(plan, "f64", [d[0] for d in dev], [d[1] for d in dev],
+                                           [d[2] for d in dev], use_graph=True)
+        for b, C in enumerate(res2.fetch(plan)):
+            h = to_host(C)
+            assert_same_structure(h, first[b])
+            assert np.array_equal(h.val, first[b].val), (rep, b)
+
+
 def test_eager_and_graph_agree(plan):
     inst = _small_batch()[:5]
     p2 = spg.Plan()
