@@ -26,9 +26,17 @@
  *     window has A(i,k) and B(k,j) stored.  Explicit zeros and entries whose
  *     value cancels to zero stay stored (Section 5 counts explicit zeros as
  *     nonzeros).  Output rows are sorted by column (Section 5.1.1).
- *   - INT64 arithmetic wraps modulo 2^64.  FP64 sums may be formed in any
- *     order (within 1e-12 relative of an ascending-k sum for the workloads
- *     here); structure, INT64 and boolean results are exact.
+ *   - INT64 arithmetic wraps modulo 2^64.  Structure, INT64 and boolean
+ *     results are exact.  FP64: every product A(i,k)*B(k,j) is rounded once
+ *     (never fused with the add), and an entry's N terms are added in an
+ *     order that may differ from ascending k.  An entry is therefore within
+ *     1e-12 relative of the ascending-k sum, or, where N is large enough for
+ *     that to fail, within gamma_{N-1} * sum|terms| + u*|S| (u = 2^-53,
+ *     gamma_k = k u / (1 - k u)) of the exact sum S of the rounded terms:
+ *     the bound the tests check against a compensated sum of the terms.
+ *     Rows with at most 64 products, one A entry, or that take the k-way
+ *     merge bin add in ascending k and match the ascending-k sum bit for
+ *     bit.
  *   - Every call is asynchronous on the plan's stream except where a
  *     parameter is a host output (those synchronize the stream).
  *   - Errors are reported only through the return code; nothing aborts or

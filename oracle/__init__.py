@@ -56,11 +56,13 @@ def _load():
                                                 P, P, ctypes.c_int]
             lib.oracle_spgemm_fill.argtypes = [ctypes.c_int, I64, P, P, P, P, P, P, I64, I64,
                                                I64, P, P, P, P, ctypes.c_int]
+            lib.oracle_spgemm_f64_check.argtypes = [I64, P, P, P, P, P, P, I64, I64, I64, P, P, P, P, P,
+                                                    ctypes.c_int]
             lib.oracle_merge_count.argtypes = [I64, I64, ctypes.c_int, P, P, P, ctypes.c_int]
             lib.oracle_merge_fill.argtypes = [ctypes.c_int, I64, I64, ctypes.c_int, P, P, P, P,
                                               P, P, ctypes.c_int]
             for f in (lib.oracle_row_flops, lib.oracle_spgemm_count, lib.oracle_spgemm_fill,
-                      lib.oracle_merge_count, lib.oracle_merge_fill):
+                      lib.oracle_spgemm_f64_check, lib.oracle_merge_count, lib.oracle_merge_fill):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -89,6 +91,23 @@ def row_flops(A: CSR, B: CSR, k_lo=None, k_hi=None) -> np.ndarray:
     out = np.zeros(A.nrows, dtype=np.int64)
     lib.oracle_row_flops(A.nrows, _p(arp), _p(acol), _p(brp), k_lo, k_hi, _p(out))
     return out
+
+
+def row_counts(A: CSR, B: CSR, k_lo=None, k_hi=None, rows=None, nthreads: int = 0) -> np.ndarray:
+    """nnz(C(i,:)) of every row (or of the rows given), structure only."""
+    lib = _load()
+    if A.ncols != B.nrows:
+        raise ValueError("inner dimensions differ")
+    k_lo, k_hi = _window(A, k_lo, k_hi)
+    arp, acol = _c(A.row_ptr, np.int64), _c(A.col, np.int32)
+    brp, bcol = _c(B.row_ptr, np.int64), _c(B.col, np.int32)
+    sel = None if rows is None else _c(rows, np.int64)
+    nsel = A.nrows if sel is None else sel.size
+    cnt = np.zeros(nsel, dtype=np.int64)
+    if lib.oracle_spgemm_count(2, B.ncols, _p(arp), _p(acol), _p(brp), _p(bcol), k_lo, k_hi, nsel, _p(sel),
+                               _p(cnt), nthreads):
+        raise MemoryError("oracle scratch allocation failed")
+    return cnt
 
 
 def _vals(M: CSR, sr: str):
@@ -164,19 +183,55 @@ def merge(layers, sr: str = "f64", nthreads: int = 0) -> CSR:
     return CSR(m, n, ptr, col, val)
 
 
-def f64_tolerance(A: CSR, B: CSR, ref: CSR, k_lo=None, k_hi=None, rows=None, nthreads=0):
-    """Per-entry bound for comparing an FP64 result summed in another order.
+def f64_check(A: CSR, B: CSR, ref: CSR, k_lo=None, k_hi=None, rows=None, nthreads=0):
+    """Per-entry data for checking an FP64 product summed in another order.
 
-    Returns (abs_sum, nterms): the oracle product of |A| and |B| and the
-    number of terms of each entry (the all-ones integer product), aligned
-    with ``ref``.  Two recursive summations of the same N terms in different
-    orders differ by at most 2*(N-1)*u*sum|terms| (u = 2^-53), plus one
-    rounding per product on each side."""
-    Aa = CSR(A.nrows, A.ncols, A.row_ptr, A.col, np.abs(A.val))
-    Ba = CSR(B.nrows, B.ncols, B.row_ptr, B.col, np.abs(B.val))
-    s = spgemm(Aa, Ba, "f64", k_lo, k_hi, rows, nthreads)
-    A1 = CSR(A.nrows, A.ncols, A.row_ptr, A.col, np.ones(A.nnz, np.int64))
-    B1 = CSR(B.nrows, B.ncols, B.row_ptr, B.col, np.ones(B.nnz, np.int64))
-    t = spgemm(A1, B1, "i64", k_lo, k_hi, rows, nthreads)
-    assert np.array_equal(s.col, ref.col) and np.array_equal(t.col, ref.col)
-    return s.val, t.val
+    ``ref`` is the oracle's product of A and B over the same window and rows
+    (its structure fixes the entry order).  Returns three arrays aligned with
+    ``ref.col``:
+
+    comp    the entry's terms A(i,k)*B(k,j), each rounded once, added in
+            ascending k with Neumaier's compensated summation: within
+            u*|S| + (N-1)^2 u^2 sum|terms| of their exact sum S
+            (u = 2^-53, N terms);
+    abs_sum the sum of the terms' magnitudes;
+    nterms  N, the number of terms.
+
+    Any order of N-1 additions of the same rounded terms lands within
+    (N-1) u / (1 - (N-1) u) * sum|terms| of S (the recursive-summation
+    bound), so a result and comp differ by at most that plus u*|comp| and
+    second-order terms (``f64_bound``)."""
+    lib = _load()
+    if A.ncols != B.nrows:
+        raise ValueError("inner dimensions differ")
+    k_lo, k_hi = _window(A, k_lo, k_hi)
+    arp, acol, av = _c(A.row_ptr, np.int64), _c(A.col, np.int32), _c(A.val, np.float64)
+    brp, bcol, bv = _c(B.row_ptr, np.int64), _c(B.col, np.int32), _c(B.val, np.float64)
+    sel = None if rows is None else _c(rows, np.int64)
+    nsel = A.nrows if sel is None else sel.size
+    ptr = _c(ref.row_ptr, np.int64)
+    assert ptr.size == nsel + 1
+    nz = int(ptr[-1])
+    comp = np.zeros(nz, dtype=np.float64)
+    absum = np.zeros(nz, dtype=np.float64)
+    nterms = np.zeros(nz, dtype=np.int64)
+    rc = lib.oracle_spgemm_f64_check(B.ncols, _p(arp), _p(acol), _p(av), _p(brp), _p(bcol), _p(bv), k_lo, k_hi,
+                                     nsel, _p(sel), _p(ptr), _p(comp), _p(absum), _p(nterms), nthreads)
+    if rc:
+        raise MemoryError("oracle scratch allocation failed")
+    return comp, absum, nterms
+
+
+U = 2.0 ** -53
+
+
+def f64_bound(comp, abs_sum, nterms):
+    """Largest |g - comp| of a value g that sums the same N rounded terms in
+    any order: gamma_{N-1} * sum|terms| (recursive summation in any order)
+    plus u*|comp| and 2 gamma_{N-1}^2 * sum|terms| for comp's own error, with
+    gamma_k = k u / (1 - k u); sum|terms| is taken as abs_sum * (1 + 2 gamma)
+    to cover abs_sum's own rounding."""
+    n1 = np.maximum(np.asarray(nterms, dtype=np.float64) - 1.0, 0.0)
+    g = n1 * U / (1.0 - n1 * U)
+    a = np.asarray(abs_sum, dtype=np.float64) * (1.0 + 2.0 * g)
+    return g * a + U * np.abs(np.asarray(comp)) + 2.0 * g * g * a

@@ -186,6 +186,98 @@ int oracle_spgemm_fill(int sr, int64_t n, const int64_t* a_rp, const int32_t* a_
                        NULL, out_ptr, out_col, out_val, nthreads);
 }
 
+/* FP64 parity support.  For every stored entry of the product, in the
+ * oracle's output order (rows as selected, columns ascending):
+ *   comp   the terms A(i,k)*B(k,j) (each rounded once, as every product is)
+ *          added in ascending k with Neumaier's compensated summation, so
+ *          comp is within about one rounding of their exact sum;
+ *   absum  the sum of |A(i,k)*B(k,j)| over the same terms;
+ *   nterms the number of terms.
+ * A result summed in any other order from the same rounded terms differs
+ * from their exact sum by at most (nterms-1)*u*absum to first order
+ * (u = 2^-53, the standard bound for recursive summation).  out_ptr as for
+ * the fill pass; the selected rows' structure must be that of the fill
+ * pass. */
+static void check_row(int64_t i, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
+                      const int64_t* b_rp, const int32_t* b_col, const double* b_val, int64_t k_lo,
+                      int64_t k_hi, uint8_t* mark, double* sum, double* comp, double* absum,
+                      int64_t* nterms, int32_t* touched, double* comp_out, double* abs_out,
+                      int64_t* nterms_out) {
+    int64_t nt = 0;
+    for (int64_t p = a_rp[i]; p < a_rp[i + 1]; ++p) {
+        int64_t k = a_col[p];
+        if (k < k_lo || k >= k_hi) continue;
+        for (int64_t q = b_rp[k]; q < b_rp[k + 1]; ++q) {
+            int32_t j = b_col[q];
+            double t = a_val[p] * b_val[q];
+            if (!mark[j]) {
+                mark[j] = 1;
+                sum[j] = t;
+                comp[j] = 0.0;
+                absum[j] = t < 0 ? -t : t;
+                nterms[j] = 1;
+                touched[nt++] = j;
+            } else {
+                /* Neumaier: the rounding error of s + t, recovered exactly
+                 * from the larger operand, accumulates in comp */
+                double s = sum[j];
+                double r = s + t;
+                double as = s < 0 ? -s : s, at = t < 0 ? -t : t;
+                if (as >= at) comp[j] += (s - r) + t;
+                else comp[j] += (t - r) + s;
+                sum[j] = r;
+                absum[j] += at;
+                nterms[j] += 1;
+            }
+        }
+    }
+    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+    for (int64_t t = 0; t < nt; ++t) {
+        int32_t j = touched[t];
+        comp_out[t] = sum[j] + comp[j];
+        abs_out[t] = absum[j];
+        nterms_out[t] = nterms[j];
+        mark[j] = 0;
+    }
+}
+
+int oracle_spgemm_f64_check(int64_t n, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
+                            const int64_t* b_rp, const int32_t* b_col, const double* b_val,
+                            int64_t k_lo, int64_t k_hi, int64_t nsel, const int64_t* rows,
+                            const int64_t* out_ptr, double* comp_out, double* abs_out,
+                            int64_t* nterms_out, int nthreads) {
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads) reduction(| : err)
+#endif
+    {
+        size_t nn = (size_t)(n > 0 ? n : 1);
+        uint8_t* mark = (uint8_t*)calloc(nn, 1);
+        double* sum = (double*)malloc(sizeof(double) * nn);
+        double* comp = (double*)malloc(sizeof(double) * nn);
+        double* absum = (double*)malloc(sizeof(double) * nn);
+        int64_t* nterms = (int64_t*)malloc(sizeof(int64_t) * nn);
+        int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * nn);
+        int ok = mark && sum && comp && absum && nterms && touched;
+        if (!ok) err = 1;
+        {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+            for (int64_t r = 0; r < nsel; ++r) {
+                if (!ok) continue;
+                int64_t i = rows ? rows[r] : r;
+                int64_t o = out_ptr[r];
+                check_row(i, a_rp, a_col, a_val, b_rp, b_col, b_val, k_lo, k_hi, mark, sum, comp, absum,
+                          nterms, touched, comp_out + o, abs_out + o, nterms_out + o);
+            }
+        }
+        free(mark); free(sum); free(comp); free(absum); free(nterms); free(touched);
+    }
+    return err ? -1 : 0;
+}
+
 /* Merge of c layers (all m x n, canonical).  Same accumulator; the layers
  * are visited in ascending order, so equal (i,j) fold in layer order. */
 static int64_t merge_row(int sr, int64_t i, int c, const int64_t* const* rps,

@@ -31,8 +31,16 @@ template <int SR> struct Sr;
 template <> struct Sr<SR_F64> {
     typedef double acc_t;
     __device__ static inline acc_t load(const void* v, int64_t p) { return ((const double*)v)[p]; }
-    __device__ static inline acc_t mul(acc_t a, acc_t b) { return a * b; }
-    __device__ static inline acc_t add(acc_t a, acc_t b) { return a + b; }
+    // every product is rounded on its own and never fused with the add that
+    // takes it (no FMA contraction): the terms are those of the definition
+    __device__ static inline acc_t mul(acc_t a, acc_t b) {
+#pragma clang fp contract(off)
+        return a * b;
+    }
+    __device__ static inline acc_t add(acc_t a, acc_t b) {
+#pragma clang fp contract(off)
+        return a + b;
+    }
     __device__ static inline acc_t zero() { return 0.0; }
     __device__ static inline void lds_add(acc_t* p, acc_t v) {
         __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);

@@ -612,7 +612,11 @@ __global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const
         const RankItem item = items[it];
         const int64_t i = rows[item.r];
         const uint32_t* src = bm_save + (int64_t)heavy_idx[i] * nwords + (int64_t)item.c0 * WPC;
-        const int nw = (item.c1 - item.c0) * WPC;
+        // the last chunk of a row may be partial (n not a multiple of W): the
+        // saved bitmap ends at nwords, so stage no word past it (columns of
+        // the missing words are >= n and never looked up)
+        const int nw_full = (item.c1 - item.c0) * WPC, nw_left = nwords - item.c0 * WPC;
+        const int nw = nw_full < nw_left ? nw_full : nw_left;
         const int64_t off = c_rp.off(i) + item.roff;
         const int32_t cbase = item.c0 * W;
         // packed words and columns
@@ -625,10 +629,15 @@ __global__ void __launch_bounds__(NT) k_num_rankc(Csr A, Csr B, int32_t W, const
             a_beg[i], a_end[i], L,
             [&](int64_t p, int64_t& bs, int32_t& len) {
                 const int64_t k = A.col[p];
-                const int32_t* sp = split + k * (P + 1);
                 const int64_t rs = B.rp[k];
-                bs = rs + sp[c0];
-                len = sp[c1] - sp[c0];
+                if (split) {
+                    const int32_t* sp = split + k * (P + 1);
+                    bs = rs + sp[c0];
+                    len = sp[c1] - sp[c0];
+                } else {  // one chunk covers all columns: the whole B row (no split table)
+                    bs = rs;
+                    len = (int32_t)(B.rp[k + 1] - rs);
+                }
             },
             [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
             [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },

@@ -87,6 +87,7 @@ struct RowInfoOut {
     int64_t* bin_stats;  // [3][NBINS]: rows, flops, A entries
     int32_t* long_rows;  // queue of rows with more than LONG_ROW entries
     int32_t* long_count;
+    unsigned long long* max_flops;  // largest flops_i over the rows (one value)
 };
 
 __device__ inline int64_t lower_bound_col(const int32_t* col, int64_t lo, int64_t hi, int64_t key) {
@@ -99,7 +100,7 @@ __device__ inline int64_t lower_bound_col(const int32_t* col, int64_t lo, int64_
 
 __device__ inline void finish_row(int64_t i, int64_t beg, int64_t end, int64_t f, int32_t mb,
                                   const BinParams& bp, const RowInfoOut& o, int* s_hist,
-                                  int64_t* s_flops, int64_t* s_annz) {
+                                  int64_t* s_flops, int64_t* s_annz, unsigned long long* s_fmax) {
     o.a_beg[i] = beg;
     o.a_end[i] = end;
     o.flops[i] = f;
@@ -111,10 +112,12 @@ __device__ inline void finish_row(int64_t i, int64_t beg, int64_t end, int64_t f
     atomicAdd(&s_hist[b], 1);
     atomicAdd((unsigned long long*)&s_flops[b], (unsigned long long)f);
     atomicAdd((unsigned long long*)&s_annz[b], (unsigned long long)(end - beg));
+    atomicMax(s_fmax, (unsigned long long)f);
 }
 
 __device__ inline void flush_stats(const RowInfoOut& o, int* s_hist, int64_t* s_flops,
-                                   int64_t* s_annz) {
+                                   int64_t* s_annz, unsigned long long* s_fmax) {
+    if (threadIdx.x == 0 && *s_fmax) atomicMax(o.max_flops, *s_fmax);
     if (threadIdx.x < NBINS) {
         int b = threadIdx.x;
         if (s_hist[b]) {
@@ -127,7 +130,7 @@ __device__ inline void flush_stats(const RowInfoOut& o, int* s_hist, int64_t* s_
 
 __device__ inline void rowinfo_row(const Csr& A, const Csr& B, int64_t k_lo, int64_t k_hi, int full_window,
                                    const BinParams& bp, const RowInfoOut& o, int64_t i, int gl, int* s_hist,
-                                   int64_t* s_flops, int64_t* s_annz);
+                                   int64_t* s_flops, int64_t* s_annz, unsigned long long* s_fmax);
 
 // 256 threads = 16 groups of 16 lanes, one row per group; the grid strides
 // over groups of 16 rows (few workgroups, so few global statistics atomics).
@@ -135,22 +138,24 @@ __global__ void __launch_bounds__(256) k_rowinfo(Csr A, Csr B, int64_t k_lo, int
                                                  int full_window, BinParams bp, RowInfoOut o) {
     __shared__ int s_hist[NBINS];
     __shared__ int64_t s_flops[NBINS], s_annz[NBINS];
+    __shared__ unsigned long long s_fmax;
     if (threadIdx.x < NBINS) {
         s_hist[threadIdx.x] = 0;
         s_flops[threadIdx.x] = 0;
         s_annz[threadIdx.x] = 0;
     }
+    if (threadIdx.x == 0) s_fmax = 0;
     __syncthreads();
     const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
     for (int64_t i0 = (int64_t)blockIdx.x * 16; i0 < A.nrows; i0 += (int64_t)gridDim.x * 16)
-        rowinfo_row(A, B, k_lo, k_hi, full_window, bp, o, i0 + g, gl, s_hist, s_flops, s_annz);
+        rowinfo_row(A, B, k_lo, k_hi, full_window, bp, o, i0 + g, gl, s_hist, s_flops, s_annz, &s_fmax);
     __syncthreads();
-    flush_stats(o, s_hist, s_flops, s_annz);
+    flush_stats(o, s_hist, s_flops, s_annz, &s_fmax);
 }
 
 __device__ inline void rowinfo_row(const Csr& A, const Csr& B, int64_t k_lo, int64_t k_hi, int full_window,
                                    const BinParams& bp, const RowInfoOut& o, int64_t i, int gl, int* s_hist,
-                                   int64_t* s_flops, int64_t* s_annz) {
+                                   int64_t* s_flops, int64_t* s_annz, unsigned long long* s_fmax) {
     bool active = i < A.nrows;
     int64_t beg = 0, end = 0;
     if (active) {
@@ -186,7 +191,7 @@ __device__ inline void rowinfo_row(const Csr& A, const Csr& B, int64_t k_lo, int
         int32_t o2 = __shfl_xor(mb, d, SPG_WAVE);
         mb = o2 > mb ? o2 : mb;
     }
-    if (active && gl == 0) finish_row(i, beg, end, f, mb, bp, o, s_hist, s_flops, s_annz);
+    if (active && gl == 0) finish_row(i, beg, end, f, mb, bp, o, s_hist, s_flops, s_annz, s_fmax);
 }
 
 // One 256-thread workgroup per queued long row, grid-stride over the queue.
@@ -197,11 +202,13 @@ __global__ void __launch_bounds__(256) k_rowinfo_long(Csr A, Csr B, int64_t k_lo
     __shared__ int64_t s_flops[NBINS], s_annz[NBINS];
     __shared__ int64_t s_red[8];
     __shared__ int32_t s_redm[8];
+    __shared__ unsigned long long s_fmax;
     if (threadIdx.x < NBINS) {
         s_hist[threadIdx.x] = 0;
         s_flops[threadIdx.x] = 0;
         s_annz[threadIdx.x] = 0;
     }
+    if (threadIdx.x == 0) s_fmax = 0;
     __syncthreads();
     const int nq = *o.long_count;
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {
@@ -234,11 +241,11 @@ __global__ void __launch_bounds__(256) k_rowinfo_long(Csr A, Csr B, int64_t k_lo
                 tf += s_red[x];
                 tm = s_redm[x] > tm ? s_redm[x] : tm;
             }
-            finish_row(i, beg, end, tf, tm, bp, o, s_hist, s_flops, s_annz);
+            finish_row(i, beg, end, tf, tm, bp, o, s_hist, s_flops, s_annz, &s_fmax);
         }
         __syncthreads();
     }
-    flush_stats(o, s_hist, s_flops, s_annz);
+    flush_stats(o, s_hist, s_flops, s_annz, &s_fmax);
 }
 
 // Numeric classification from exact counts (after the symbolic scan).

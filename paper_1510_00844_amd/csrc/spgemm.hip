@@ -654,7 +654,7 @@ static spg_status ensure_rows(spg_plan P, int64_t m) {
     SPG_TRY(P->lpt_hist.ensure(sizeof(int32_t) * LPT_MAX_BINS * LPT_KEYS, "work order"));
     SPG_TRY(P->long_rows.ensure(4 * mm, "long rows"));
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
-    SPG_TRY(P->stats.ensure(sizeof(int64_t) * 4 * NBINS, "bin stats"));
+    SPG_TRY(P->stats.ensure(sizeof(int64_t) * (4 * NBINS + 8), "bin stats"));
     return SPG_OK;
 }
 
@@ -683,6 +683,18 @@ static BinParams bin_params(spg_plan P, int64_t n) {
             }
     }
     return bp;
+}
+
+// The product enumerators count a batch's products (the B-row lengths of up
+// to 1024 A entries) in int32.  With n <= 2^19 (one LDS bitmap per row) a B
+// row holds at most 2^19 entries and a batch stays below 2^29; with wider B
+// the rows that enumerate whole B rows (hash bins) are bounded by their own
+// products, so a product whose heaviest row has 2^31 or more products is
+// rejected there.
+static spg_status check_row_products(const BinParams& bp, int64_t max_row_flops) {
+    if (!bp.dense_ok && max_row_flops >= (1ll << 31) - 1)
+        return fail(SPG_ERR_INDEX_RANGE, "a row has 2^31 or more products and B has more than 2^19 columns");
+    return SPG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -737,10 +749,11 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     int64_t* cnt = c_row_ptr + 1;
     const int full = (k_lo == 0 && k_hi == A->ncols) ? 1 : 0;
 
-    SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
+    SPG_TRY(fill_i64(P, stats, 4 * NBINS + 1, 0));
     SPG_TRY(fill_i32(P, ctr, 1 + NBINS, 0));
     RowInfoOut o{P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), P->flops.as<int64_t>(), P->maxb.as<int32_t>(),
-                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr};
+                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr,
+                 (unsigned long long*)(stats + 4 * NBINS)};
     if (m > 0) {
         SPG_TRY(launch(P, "rowinfo", [&] {
             k_rowinfo<<<(unsigned)std::min<int64_t>(grid_for(m, 16), 4096), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
@@ -755,8 +768,11 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
     }
     if (!P->frozen) {
         HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 3 * NBINS, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipMemcpyAsync(P->h_stats + 3 * NBINS, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               P->stream));
         HIP_TRY(hipStreamSynchronize(P->stream));
         std::memcpy(P->sym_counts, P->h_stats, sizeof(int64_t) * 3 * NBINS);
+        SPG_TRY(check_row_products(bp, P->h_stats[3 * NBINS]));
     }
     int64_t tot = 0;
     for (int x = 0; x < NBINS; ++x) tot += P->sym_counts[NBINS + x];
@@ -945,10 +961,12 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
             }));
         } else if (bb == BIN_DENSE_PAR) {
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
-            // an item holds at least one whole chunk (<= W outputs); group as
-            // many chunks as the LDS allows, up to RANKC_GROUP
-            // outputs per item: at least one whole chunk (<= W outputs)
-            const int32_t RC = W < RANKC_CAP ? W : std::max(RANKC_CAP, W);
+            // outputs per item: RANKC_CAP, and at least one whole chunk (<= W
+            // outputs), so every item holds at least one chunk; fewer when the
+            // LDS of the smallest item (one chunk's words + RC values) would
+            // not fit
+            int32_t RC = std::max(RANKC_CAP, W);
+            while (RC > W && (int64_t)(W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) RC /= 2;
             // chunks per item: about RC outputs at the bin's mean density,
             // at most chunk_group
             const double per_chunk = (double)P->num_counts[3 * NBINS + bb] / ((double)nr * chunks);
@@ -1449,10 +1467,11 @@ extern "C" spg_status spgemm_learned_run(spg_plan P, spg_semiring sr, const spg_
     int32_t* ctr = P->small_i32.as<int32_t>();
     int64_t* cnt = P->lcnt.as<int64_t>() + 1;
     const int full = (k_lo == 0 && k_hi == A->ncols) ? 1 : 0;
-    SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
+    SPG_TRY(fill_i64(P, stats, 4 * NBINS + 1, 0));
     SPG_TRY(fill_i32(P, ctr, 2 + NBINS, 0));
     RowInfoOut o{P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), P->flops.as<int64_t>(), P->maxb.as<int32_t>(),
-                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr};
+                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr,
+                 (unsigned long long*)(stats + 4 * NBINS)};
     LearnedParams lp;
     lp.margin = margin;
     lp.use_mlp = mlp_params ? 1 : 0;
@@ -1482,7 +1501,10 @@ extern "C" spg_status spgemm_learned_run(spg_plan P, spg_semiring sr, const spg_
     HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 2 * NBINS, hipMemcpyDeviceToHost, P->stream));
     HIP_TRY(hipMemcpyAsync(P->h_stats + 2 * NBINS, P->slot.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost,
                            P->stream));
+    HIP_TRY(hipMemcpyAsync(P->h_stats + 2 * NBINS + 1, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
+    SPG_TRY(check_row_products(bp, P->h_stats[2 * NBINS + 1]));
     std::memcpy(P->l_counts, P->h_stats, sizeof(int64_t) * 2 * NBINS);
     P->l_slots = P->h_stats[2 * NBINS];
     P->l_nexact = P->l_counts[BIN_DENSE];

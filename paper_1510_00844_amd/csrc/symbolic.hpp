@@ -11,6 +11,7 @@
 //            structural part of the sparse accumulator of Section 3.
 #pragma once
 #include "products.hpp"
+#include "rowinfo.hpp"
 
 namespace spg {
 
@@ -232,18 +233,24 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
         for (int64_t cb = 0; cb < B.ncols; cb += block_cols) {
             for (int t = threadIdx.x; t < nwords; t += NT) bm[t] = 0u;
             __syncthreads();
+            // each B row restricted to the block's columns by binary search:
+            // a block gathers only its own products, and a segment never
+            // exceeds block_cols entries (the batch sums stay in int32)
             for_each_product_gm<NT, GM>(
                 a_beg[i], a_end[i], L,
                 [&](int64_t p, int64_t& bs, int32_t& len) {
-                    int64_t k = A.col[p];
-                    bs = B.rp[k];
-                    len = (int32_t)(B.rp[k + 1] - bs);
+                    const int64_t k = A.col[p];
+                    const int64_t rs = B.rp[k], re = B.rp[k + 1];
+                    const int64_t lo = lower_bound_col(B.col, rs, re, cb);
+                    const int64_t hi = lower_bound_col(B.col, lo, re, cb + block_cols);
+                    bs = lo;
+                    len = (int32_t)(hi - lo);
                 },
                 [&](int, int64_t) {},
                 [&](int64_t q) { return (int64_t)B.col[q]; },
                 [&](int, int64_t j) {
                     const int64_t jj = j - cb;
-                    if (jj >= 0 && jj < block_cols) atomicOr(&bm[jj >> 5], 1u << (jj & 31));
+                    atomicOr(&bm[jj >> 5], 1u << (jj & 31));
                 });
             int32_t mine = 0;
             for (int t = threadIdx.x; t < nwords; t += NT) mine += __popc(bm[t]);

@@ -17,3 +17,22 @@ def pytest_configure(config):
 def gpu_available():
     import torch
     return torch.cuda.is_available()
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """FP64 entries over 1e-12 relative that each test re-checked against the
+    compensated sum of their terms (always printed, also under -q)."""
+    try:
+        from util import FP64_RECHECKS
+    except ImportError:
+        return
+    if not FP64_RECHECKS:
+        return
+    per = {}
+    for test, over, total in FP64_RECHECKS:
+        o, t = per.get(test, (0, 0))
+        per[test] = (o + over, t + total)
+    tr = terminalreporter
+    tr.write_sep("-", "FP64 entries over 1e-12 relative (re-checked against the compensated sum)")
+    for test, (o, t) in per.items():
+        tr.write_line("%s: %d of %d entries" % (test, o, t))

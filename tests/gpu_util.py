@@ -54,8 +54,7 @@ def check_rows_vs_oracle(C: spg.DeviceCSR, A: CSR, B: CSR, sr: str, rows, k_lo=N
     ref = oracle.spgemm(A, B, sr, k_lo, k_hi, rows=rows)
     assert_same_structure(got, ref)
     if sr == "f64":
-        s, t = oracle.f64_tolerance(A, B, ref, k_lo, k_hi, rows=rows)
-        return assert_values(got, ref, sr, abs_sum=s, nterms=t)
+        return assert_values(got, ref, sr, lambda: oracle.f64_check(A, B, ref, k_lo, k_hi, rows=rows))
     return assert_values(got, ref, sr)
 
 
@@ -64,8 +63,7 @@ def check_full_vs_oracle(C: spg.DeviceCSR, A: CSR, B: CSR, sr: str, k_lo=None, k
     ref = oracle.spgemm(A, B, sr, k_lo, k_hi)
     assert_same_structure(got, ref)
     if sr == "f64":
-        s, t = oracle.f64_tolerance(A, B, ref, k_lo, k_hi)
-        return assert_values(got, ref, sr, abs_sum=s, nterms=t)
+        return assert_values(got, ref, sr, lambda: oracle.f64_check(A, B, ref, k_lo, k_hi))
     return assert_values(got, ref, sr)
 
 
@@ -80,3 +78,25 @@ def sample_rows(A: CSR, B: CSR, count: int, seed: int, k_lo=None, k_hi=None):
     rng = np.random.default_rng(seed)
     rnd = rng.choice(A.nrows, size=min(A.nrows, count // 2), replace=False)
     return np.unique(np.concatenate([heavy, light, rnd]))
+
+
+def check_blocks_vs_oracle(C: spg.DeviceCSR, A: CSR, B: CSR, sr: str, rows, block_entries=60_000_000,
+                           k_lo=None, k_hi=None):
+    """Every given row of the device result against the oracle, in row
+    blocks of about block_entries outputs (bounded host memory).  Returns
+    (rows compared, entries compared, FP64 entries that needed the re-check)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    rp = C.row_ptr.cpu().numpy()
+    lens = rp[rows + 1] - rp[rows]
+    ent = over = 0
+    s = 0
+    while s < rows.size:
+        e = s + 1
+        tot = int(lens[s])
+        while e < rows.size and tot + lens[e] <= block_entries:
+            tot += int(lens[e])
+            e += 1
+        over += check_rows_vs_oracle(C, A, B, sr, rows[s:e], k_lo, k_hi) or 0
+        ent += tot
+        s = e
+    return rows.size, ent, over
