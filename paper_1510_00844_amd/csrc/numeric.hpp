@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
     V vals[SMALL_ROWS];
     uint64_t keys[SMALL_ROWS];
     int64_t row[SMALL_ROWS];
-    for_small_rows(A, B, rows, nrows, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t p, int64_t q) {
+    for_small_rows(A, B, rows, nrows, w, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t p, int64_t q) {
         row[u] = i;
         vals[u] = S::zero();
         keys[u] = ~0ull;
@@ -552,40 +552,66 @@ struct RankItem {
     int64_t roff;   // outputs of the row before the item
 };
 
-__global__ void __launch_bounds__(256) k_rank_items(const int32_t* rows, int32_t nrows, const int32_t* heavy_idx,
-                                                    const int32_t* chunk_cnt, int32_t P, int32_t RC, int32_t G,
+// Chunks per rank-chunk item: about RC outputs at the bin's mean density
+// (cnnz outputs over nr rows of `chunks` chunks), at most chunk_group and
+// `chunks`, and no more than the LDS holds (G*W/32 packed words + RC
+// values + static_lds <= max_lds).  Integer arithmetic, so the host (sizing
+// the launch) and the device (forming the items) agree.
+__host__ __device__ inline int32_t rankc_group(int64_t nr, int64_t cnnz, int32_t chunks, int32_t RC, int32_t chunk_group,
+                                               int32_t W, int64_t static_lds, int64_t max_lds) {
+    int64_t G = cnnz > 0 ? (2 * (int64_t)RC * nr * chunks + cnnz) / (2 * cnnz) : chunks;
+    if (G > chunks) G = chunks;
+    if (G > chunk_group) G = chunk_group;
+    if (G < 1) G = 1;
+    while (G > 1 && G * (W / 32) * 8 + (int64_t)RC * 8 + static_lds > max_lds) --G;
+    return (int32_t)G;
+}
+
+// Work items of the rank-chunk bin, located on the device (counts of the
+// numeric classification): each row's chunks grouped greedily into items
+// of at most RC outputs and G chunks.
+__global__ void __launch_bounds__(256) k_rank_items(BinRef ref, const int32_t* heavy_idx, const int32_t* chunk_cnt,
+                                                    int32_t P, int32_t RC, int32_t chunk_group, int32_t W,
+                                                    int64_t static_lds, int64_t max_lds, const int64_t* cnnz_of_bin,
                                                     RankItem* items, int32_t* nitems) {
     __shared__ int32_t tmp[256 / SPG_WAVE + 1];
     __shared__ int32_t s_base;
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    const int32_t* cc = r < nrows ? chunk_cnt + (int64_t)heavy_idx[rows[r]] * P : nullptr;
-    // the greedy grouping of the row's chunks, walked twice: to count the
-    // items (one global add per workgroup reserves their slots), then to
-    // write them
-    auto walk = [&](auto emit) {
-        int64_t roff = 0;
-        int c0 = 0;
-        while (c0 < P) {
-            int c1 = c0;
-            int32_t n = 0;
-            while (c1 < P && c1 - c0 < G && n + cc[c1] <= RC) n += cc[c1++];
-            if (c1 == c0) {  // a chunk above RC (the host keeps RC >= W): take it alone, always progress
-                n = cc[c0];
-                c1 = c0 + 1;
+    const int32_t* rows;
+    int64_t nrows;
+    ref.locate(rows, nrows);
+    const int32_t G = rankc_group(nrows, *cnnz_of_bin, P, RC, chunk_group, W, static_lds, max_lds);
+    for (int64_t r0 = (int64_t)blockIdx.x * 256; r0 < nrows; r0 += (int64_t)gridDim.x * 256) {
+        const int64_t r = r0 + threadIdx.x;
+        const int32_t* cc = r < nrows ? chunk_cnt + (int64_t)heavy_idx[rows[r]] * P : nullptr;
+        // the greedy grouping of the row's chunks, walked twice: to count the
+        // items (one global add per workgroup reserves their slots), then to
+        // write them
+        auto walk = [&](auto emit) {
+            int64_t roff = 0;
+            int c0 = 0;
+            while (c0 < P) {
+                int c1 = c0;
+                int32_t n = 0;
+                while (c1 < P && c1 - c0 < G && n + cc[c1] <= RC) n += cc[c1++];
+                if (c1 == c0) {  // a chunk above RC (the host keeps RC >= W): take it alone, always progress
+                    n = cc[c0];
+                    c1 = c0 + 1;
+                }
+                if (n > 0) emit(c0, c1, n, roff);
+                roff += n;
+                c0 = c1;
             }
-            if (n > 0) emit(c0, c1, n, roff);
-            roff += n;
-            c0 = c1;
-        }
-    };
-    int32_t mine = 0;
-    if (cc) walk([&](int, int, int32_t, int64_t) { ++mine; });
-    int32_t total;
-    int32_t slot = block_exclusive_scan<256, int32_t>(mine, &total, tmp);
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(nitems, total) : 0;
-    __syncthreads();
-    slot += s_base;
-    if (cc) walk([&](int c0, int c1, int32_t n, int64_t roff) { items[slot++] = RankItem{r, c0, c1, n, roff}; });
+        };
+        int32_t mine = 0;
+        if (cc) walk([&](int, int, int32_t, int64_t) { ++mine; });
+        int32_t total;
+        int32_t slot = block_exclusive_scan<256, int32_t>(mine, &total, tmp);
+        if (threadIdx.x == 0) s_base = total ? atomicAdd(nitems, total) : 0;
+        __syncthreads();
+        slot += s_base;
+        if (cc) walk([&](int c0, int c1, int32_t n, int64_t roff) { items[slot++] = RankItem{(int32_t)r, c0, c1, n, roff}; });
+        __syncthreads();
+    }
 }
 
 // Dynamic LDS: G*W/32 packed words (prefix << 32 | bits), then RC values.

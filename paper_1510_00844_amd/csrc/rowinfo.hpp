@@ -29,7 +29,7 @@ constexpr int BIN_EMPTY = 0, BIN_TINY = 1, BIN_SMALL = 2, BIN_HASH0 = 3, BIN_DEN
 constexpr int BIN_DENSE_PAR = 11;  // numeric: column chunks of one row in parallel
 constexpr int BIN_RANK0 = 13;  // rank-space accumulator, capacity 4096 << (b - BIN_RANK0)
 constexpr int RANK_MIN_LOG2 = 12;
-constexpr int LONG_ROW = 512;
+constexpr int LONG_ROW = 128;
 constexpr int HASH_MIN_LOG2 = 7;  // 128 slots
 
 __device__ inline int ceil_log2_i64(int64_t x) {
@@ -75,6 +75,36 @@ __device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, bool sym
         return BIN_HASH0 + (lg - HASH_MIN_LOG2);
     }
     return chunks_ok ? BIN_DENSE_PAR : BIN_DENSE;
+}
+
+// The rows of one bin, located on the device: the per-bin row counts (the
+// lists of the bins below b come first in `lists`).  Kernels launched this
+// way stride over the bin's rows, so their launches need no host copy of
+// the counts (the grid only sizes the parallelism).
+struct BinRef {
+    const int64_t* counts;
+    const int32_t* lists;
+    int32_t bin;
+    __device__ inline void locate(const int32_t*& rows, int64_t& n) const {
+        int64_t off = 0;
+        for (int x = 0; x < bin; ++x) off += counts[x];
+        rows = lists + off;
+        n = counts[bin];
+    }
+};
+
+// Rows of a bin over workgroups: row r goes to workgroup r mod gridDim.x.
+// body(r, i) gets the position r in the bin list and the row i; it may use
+// barriers (all threads call it).
+template <class Body>
+__device__ inline void for_each_bin_row(const BinRef& ref, Body body) {
+    const int32_t* rows;
+    int64_t n;
+    ref.locate(rows, n);
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        body(r, (int64_t)rows[r]);
+        __syncthreads();  // the row is done with the LDS
+    }
 }
 
 struct RowInfoOut {
@@ -177,11 +207,16 @@ __device__ inline void rowinfo_row(const Csr& A, const Csr& B, int64_t k_lo, int
     int64_t f = 0;
     int32_t mb = 0;
     if (active) {
-        for (int64_t p = beg + gl; p < end; p += 16) {
-            int64_t k = A.col[p];
-            int64_t len = B.rp[k + 1] - B.rp[k];
-            f += len;
-            mb = len > mb ? (int32_t)len : mb;
+        // two A entries per lane per step, so their dependent loads overlap
+        for (int64_t p = beg + gl; p < end; p += 32) {
+            const bool two = p + 16 < end;
+            const int64_t k0 = A.col[p];
+            const int64_t k1 = two ? (int64_t)A.col[p + 16] : k0;
+            const int64_t l0 = B.rp[k0 + 1] - B.rp[k0];
+            const int64_t l1 = two ? B.rp[k1 + 1] - B.rp[k1] : 0;
+            f += l0 + l1;
+            mb = l0 > mb ? (int32_t)l0 : mb;
+            mb = l1 > mb ? (int32_t)l1 : mb;
         }
     }
     // reduce inside the 16-lane group (xor offsets < 16 stay in the group)
@@ -249,10 +284,12 @@ __global__ void __launch_bounds__(256) k_rowinfo_long(Csr A, Csr B, int64_t k_lo
 }
 
 // Numeric classification from exact counts (after the symbolic scan).
+// A bitmap row keeps its rank paths only if the symbolic pass saved its
+// bitmap (heavy_idx >= 0; NULL = no bitmaps saved).
 __global__ void __launch_bounds__(256) k_num_classify(int64_t m, const int64_t* c_rp,
                                                       const int64_t* a_beg, const int64_t* a_end,
                                                       const int64_t* flops, BinParams bp,
-                                                      uint8_t* bin, int64_t* bin_stats) {
+                                                      const int32_t* heavy_idx, uint8_t* bin, int64_t* bin_stats) {
     __shared__ int s_hist[NBINS];
     __shared__ int64_t s_flops[NBINS], s_annz[NBINS], s_cnnz[NBINS];
     if (threadIdx.x < NBINS) {
@@ -267,7 +304,8 @@ __global__ void __launch_bounds__(256) k_num_classify(int64_t m, const int64_t* 
         int64_t cnt = c_rp[i + 1] - c_rp[i];
         int64_t an = a_end[i] - a_beg[i];
         int64_t f = flops[i];
-        int b = num_bin(f, an, cnt, bin[i] == BIN_DENSE, bp);
+        const bool saved = bin[i] == BIN_DENSE && heavy_idx && heavy_idx[i] >= 0;
+        int b = num_bin(f, an, cnt, saved, bp);
         bin[i] = (uint8_t)b;
         atomicAdd(&s_hist[b], 1);
         atomicAdd((unsigned long long*)&s_flops[b], (unsigned long long)f);
@@ -333,13 +371,25 @@ __device__ inline int lpt_key(int32_t row, const uint8_t* bin, int b_lo, const i
     return ((int)bin[row] - b_lo) * LPT_KEYS + lpt_class(work[row]);
 }
 
-__global__ void __launch_bounds__(256) k_lpt_hist(const int32_t* rows, int64_t n, const uint8_t* bin, int b_lo,
-                                                  int nk, const int64_t* work, int32_t* hist) {
+// The rows of bins [b_lo, b_hi) in the lists: offset and count from the
+// per-bin counts on the device.
+__device__ inline void bin_run(const int64_t* counts, int b_lo, int b_hi, int64_t& off, int64_t& n) {
+    off = 0;
+    for (int x = 0; x < b_lo; ++x) off += counts[x];
+    n = 0;
+    for (int x = b_lo; x < b_hi; ++x) n += counts[x];
+}
+
+__global__ void __launch_bounds__(256) k_lpt_hist(const int32_t* lists, const int64_t* counts, int b_lo, int b_hi,
+                                                  const uint8_t* bin, int nk, const int64_t* work, int32_t* hist) {
     __shared__ int32_t s_h[LPT_KEYS * LPT_MAX_BINS];
+    int64_t off, n;
+    bin_run(counts, b_lo, b_hi, off, n);
+    if ((int64_t)blockIdx.x * 256 >= n) return;
     for (int k = threadIdx.x; k < nk; k += 256) s_h[k] = 0;
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r < n) atomicAdd(&s_h[lpt_key(rows[r], bin, b_lo, work)], 1);
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256)
+        atomicAdd(&s_h[lpt_key(lists[off + r], bin, b_lo, work)], 1);
     __syncthreads();
     for (int k = threadIdx.x; k < nk; k += 256)
         if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
@@ -362,23 +412,40 @@ __global__ void __launch_bounds__(256) k_lpt_scan(int32_t* hist, int nk) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_lpt_scatter(const int32_t* rows, int64_t n, const uint8_t* bin, int b_lo,
-                                                     int nk, const int64_t* work, int32_t* cursor, int32_t* out) {
+// Scatter by key; each 256-row tile of a workgroup takes its key bases with
+// one atomic per key.  tmp receives the ordered rows (n entries).
+__global__ void __launch_bounds__(256) k_lpt_scatter(const int32_t* lists, const int64_t* counts, int b_lo, int b_hi,
+                                                     const uint8_t* bin, int nk, const int64_t* work, int32_t* cursor,
+                                                     int32_t* tmp) {
     __shared__ int32_t s_cnt[LPT_KEYS * LPT_MAX_BINS];
-    for (int k = threadIdx.x; k < nk; k += 256) s_cnt[k] = 0;
-    __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int key = 0, local = 0, row = 0;
-    if (r < n) {
-        row = rows[r];
-        key = lpt_key(row, bin, b_lo, work);
-        local = atomicAdd(&s_cnt[key], 1);
+    int64_t off, n;
+    bin_run(counts, b_lo, b_hi, off, n);
+    for (int64_t t0 = (int64_t)blockIdx.x * 256; t0 < n; t0 += (int64_t)gridDim.x * 256) {
+        for (int k = threadIdx.x; k < nk; k += 256) s_cnt[k] = 0;
+        __syncthreads();
+        const int64_t r = t0 + threadIdx.x;
+        int key = 0, local = 0, row = 0;
+        if (r < n) {
+            row = lists[off + r];
+            key = lpt_key(row, bin, b_lo, work);
+            local = atomicAdd(&s_cnt[key], 1);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nk; k += 256)
+            if (s_cnt[k]) s_cnt[k] = atomicAdd(&cursor[k], s_cnt[k]);  // now the tile's base for key k
+        __syncthreads();
+        if (r < n) tmp[s_cnt[key] + local] = row;
+        __syncthreads();
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nk; k += 256)
-        if (s_cnt[k]) s_cnt[k] = atomicAdd(&cursor[k], s_cnt[k]);  // now the block's base for key k
-    __syncthreads();
-    if (r < n) out[s_cnt[key] + local] = row;
+}
+
+// The ordered rows back into the lists.
+__global__ void __launch_bounds__(256) k_lpt_copy(int32_t* lists, const int64_t* counts, int b_lo, int b_hi,
+                                                  const int32_t* tmp) {
+    int64_t off, n;
+    bin_run(counts, b_lo, b_hi, off, n);
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256)
+        lists[off + r] = tmp[r];
 }
 
 }  // namespace spg

@@ -101,6 +101,7 @@ struct spg_plan_s {
     hipEvent_t ev_fork = nullptr, ev_join[NAUX] = {};
     spg_opts opts;
     int max_lds = 65536;
+    int num_cu = 256;
 
     // per-row state of the current product
     DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
@@ -112,6 +113,14 @@ struct spg_plan_s {
     int h_layers_cap = 0;
 
     Signature sig;
+    int64_t sig_rows = 0;       // rows of the current symbolic call (bounds launch grids)
+    // saved bitmaps: slots allocated, and the bitmap rows of the last call
+    // with these operands (sizes the slots of the next one without a readback)
+    int64_t bm_cap = 0;
+    bool split_ready = false;  // the split table of the current symbolic call's B is built
+    const int64_t* last_crp = nullptr;  // row pointers of the last symbolic call
+    Signature bm_sig;
+    int64_t bm_rows = -1;
     // frozen: reuse the bin counts of the previous call with the same
     // structure instead of reading them back (no host synchronization, so the
     // calls can be captured into a HIP graph)
@@ -250,15 +259,32 @@ static std::vector<int> bins_by_work(const int64_t* rows, const int64_t* work) {
 
 static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// The row analysis strides 16 rows per workgroup step; each workgroup adds
+// its per-bin statistics to a few global counters once, and device-wide
+// atomics on one address serialize across the XCDs, so the grid is kept to
+// 1024 workgroups.
+static inline unsigned rowinfo_grid(int64_t m) { return (unsigned)std::min<int64_t>(grid_for(m, 16), 1024); }
+
 // static LDS of k_num_rank<*, 512> (A values, product offsets, scan scratch), with margin
 static const int RANK_STATIC_LDS = (int)(8 * 512 + sizeof(ProductLds<512>) + 4 * 16 + 256);
 static const int RANK_STATIC_LDS_1024 = (int)(8 * 1024 + sizeof(ProductLds<1024>) + 4 * 32 + 256);
 static int rank_static_lds(spg_plan P) { return P->opts.rank_block == 1024 ? RANK_STATIC_LDS_1024 : RANK_STATIC_LDS; }
 // rank-chunk items: at most this many outputs and this many column chunks
 static const int RANKC_CAP = 4096;
-// small counters and flags (int32): [0, 17) bin cursors, 32 the CSR check
-// flag, 48 the rank-chunk item count; one size, never reallocated
-static const int SMALL_WORDS = 64;
+// small counters and flags (int32), one size, never reallocated:
+//   [0]         long-row queue length (row analysis)
+//   [1, 17)     bin cursors of the symbolic classification
+//   [33, 49)    bin cursors of the numeric classification
+//   [96]        the CSR check flag
+//   [100]       the rank-chunk item count
+static const int SMALL_WORDS = 128;
+static const int CTR_SYM_CURSOR = 1, CTR_NUM_CURSOR = 33, CTR_CHECK = 96, CTR_RANK_ITEMS = 100;
+// per-bin statistics (int64): [0, 4 NBINS) the numeric classification (rows,
+// flops, A entries, outputs), [4 NBINS] the largest row's products,
+// [STATS_SYM, STATS_SYM + 3 NBINS) the symbolic classification (rows, flops,
+// A entries)
+static const int STATS_SYM = 4 * NBINS + 8;
+static const int STATS_WORDS = STATS_SYM + 3 * NBINS;
 
 // ---------------------------------------------------------------------------
 // public helpers
@@ -457,6 +483,9 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
         P->max_lds = lds;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cus > 0)
+        P->num_cu = cus;
     for (int k = 0; k < NAUX; ++k) {
         if (hipStreamCreateWithFlags(&P->aux[k], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&P->ev_join[k], hipEventDisableTiming) != hipSuccess) {
@@ -470,7 +499,7 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         delete P;
         return fail(SPG_ERR_HIP, "event creation failed");
     }
-    if (hipHostMalloc((void**)&P->h_stats, sizeof(int64_t) * (4 * NBINS + 8), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&P->h_stats, sizeof(int64_t) * STATS_WORDS, hipHostMallocDefault) != hipSuccess) {
         delete P;
         hipGetLastError();
         return fail(SPG_ERR_OOM, "pinned host allocation failed");
@@ -587,35 +616,37 @@ static spg_status fill_i64(spg_plan P, int64_t* p, int64_t n, int64_t v) {
     return launch(P, "fill", [&] { k_fill_i64<<<grid_for(n, 256), 256, 0, cs(P)>>>(p, n, v); });
 }
 
-// Orders the row lists of bins [b_lo, b_hi) (contiguous in P->lists from
-// bin_off[b_lo]) by decreasing products within each bin, on the plan's
-// stream before the bins are launched (counting sort, three kernels).
+// Orders the row lists of bins [b_lo, b_hi) (contiguous in P->lists) by
+// decreasing products within each bin (counting sort, four kernels), with
+// the bins located from the per-bin counts on the device: no host copy of
+// the counts is needed, and no launch depends on them.
 static_assert(NBINS - BIN_DENSE_PAR <= LPT_MAX_BINS, "the heavy numeric bins fit one work ordering");
-static spg_status order_by_work(spg_plan P, int b_lo, int b_hi, const int64_t* bin_off) {
-    const int64_t off = bin_off[b_lo], nr = bin_off[b_hi] - off;
-    if (nr < 2) return SPG_OK;
+static spg_status order_by_work(spg_plan P, int b_lo, int b_hi, const int64_t* counts, int64_t max_rows) {
+    if (max_rows < 2) return SPG_OK;
     const int nk = (b_hi - b_lo) * LPT_KEYS;
-    int32_t* rows = P->lists.as<int32_t>() + off;
+    int32_t* lists = P->lists.as<int32_t>();
     int32_t* hist = P->lpt_hist.as<int32_t>();
     int32_t* tmp = P->lpt_tmp.as<int32_t>();
     const int64_t* work = P->flops.as<int64_t>();
     const uint8_t* bin = P->bin.as<uint8_t>();
+    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(max_rows, 256), 1024);
     SPG_TRY(fill_i32(P, hist, nk, 0));
     SPG_TRY(launch(P, "work_order", [&] {
-        k_lpt_hist<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, bin, b_lo, nk, work, hist);
+        k_lpt_hist<<<grid, 256, 0, cs(P)>>>(lists, counts, b_lo, b_hi, bin, nk, work, hist);
     }));
     SPG_TRY(launch(P, "work_order", [&] { k_lpt_scan<<<1, 256, 0, cs(P)>>>(hist, nk); }));
     SPG_TRY(launch(P, "work_order", [&] {
-        k_lpt_scatter<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, nr, bin, b_lo, nk, work, hist, tmp);
+        k_lpt_scatter<<<grid, 256, 0, cs(P)>>>(lists, counts, b_lo, b_hi, bin, nk, work, hist, tmp);
     }));
-    HIP_TRY(hipMemcpyAsync(rows, tmp, sizeof(int32_t) * (size_t)nr, hipMemcpyDeviceToDevice, cs(P)));
+    SPG_TRY(launch(P, "work_order", [&] { k_lpt_copy<<<grid, 256, 0, cs(P)>>>(lists, counts, b_lo, b_hi, tmp); }));
     return SPG_OK;
 }
+
 
 static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
     if (M->nrows == 0) return SPG_OK;
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "flags"));
-    int32_t* bad = P->small_i32.as<int32_t>() + 32;
+    int32_t* bad = P->small_i32.as<int32_t>() + CTR_CHECK;
     SPG_TRY(fill_i32(P, bad, 1, 0));
     Csr v = view(M);
     SPG_TRY(launch(P, "validate", [&] { k_validate<<<grid_for(M->nrows, 256), 256, 0, cs(P)>>>(v, bad); }));
@@ -654,7 +685,7 @@ static spg_status ensure_rows(spg_plan P, int64_t m) {
     SPG_TRY(P->lpt_hist.ensure(sizeof(int32_t) * LPT_MAX_BINS * LPT_KEYS, "work order"));
     SPG_TRY(P->long_rows.ensure(4 * mm, "long rows"));
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
-    SPG_TRY(P->stats.ensure(sizeof(int64_t) * (4 * NBINS + 8), "bin stats"));
+    SPG_TRY(P->stats.ensure(sizeof(int64_t) * STATS_WORDS, "bin stats"));
     return SPG_OK;
 }
 
@@ -701,30 +732,92 @@ static spg_status check_row_products(const BinParams& bp, int64_t max_row_flops)
 // symbolic
 // ---------------------------------------------------------------------------
 template <int NT, int LOG2T>
-static spg_status launch_sym_hash(spg_plan P, Csr A, Csr B, const int32_t* rows, int64_t nr, int64_t* cnt) {
+static spg_status launch_sym_hash(spg_plan P, Csr A, Csr B, BinRef ref, int64_t rows, int64_t* cnt) {
     const int64_t* ab = P->a_beg.as<int64_t>();
     const int64_t* ae = P->a_end.as<int64_t>();
+    const unsigned grid = (unsigned)std::max<int64_t>(rows, 1);  // a workgroup per row
     return launch(P, "sym_hash" + std::to_string(1 << LOG2T), [&] {
-        k_sym_hash<NT, LOG2T><<<(unsigned)nr, NT, 0, cs(P)>>>(A, B, rows, ab, ae, cnt);
+        k_sym_hash<NT, LOG2T><<<grid, NT, 0, cs(P)>>>(A, B, ref, ab, ae, cnt);
     });
 }
 
-static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int32_t* rows, int64_t nr, int64_t* cnt) {
+static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, BinRef ref, int64_t rows, int64_t* cnt) {
     switch (lg) {
-        case 7: return launch_sym_hash<64, 7>(P, A, B, rows, nr, cnt);
-        case 8: return launch_sym_hash<64, 8>(P, A, B, rows, nr, cnt);
-        case 9: return launch_sym_hash<64, 9>(P, A, B, rows, nr, cnt);
-        case 10: return launch_sym_hash<128, 10>(P, A, B, rows, nr, cnt);
-        case 11: return launch_sym_hash<256, 11>(P, A, B, rows, nr, cnt);
-        case 12: return launch_sym_hash<512, 12>(P, A, B, rows, nr, cnt);
-        case 13: return launch_sym_hash<512, 13>(P, A, B, rows, nr, cnt);
-        case 14: return launch_sym_hash<1024, 14>(P, A, B, rows, nr, cnt);
+        case 7: return launch_sym_hash<64, 7>(P, A, B, ref, rows, cnt);
+        case 8: return launch_sym_hash<64, 8>(P, A, B, ref, rows, cnt);
+        case 9: return launch_sym_hash<64, 9>(P, A, B, ref, rows, cnt);
+        case 10: return launch_sym_hash<128, 10>(P, A, B, ref, rows, cnt);
+        case 11: return launch_sym_hash<256, 11>(P, A, B, ref, rows, cnt);
+        case 12: return launch_sym_hash<512, 12>(P, A, B, ref, rows, cnt);
+        case 13: return launch_sym_hash<512, 13>(P, A, B, ref, rows, cnt);
+        case 14: return launch_sym_hash<1024, 14>(P, A, B, ref, rows, cnt);
     }
     return fail(SPG_ERR_ARG, "bad hash bin");
 }
 
+// The numeric pass's column chunks: split[k (P+1) + c] = offset in B(k,:) of
+// the first entry at column >= c W.  Depends on B and W only.
+static spg_status build_split_table(spg_plan P, Csr b, int32_t W) {
+    const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
+    const int64_t entries = b.nrows * (int64_t)(chunks + 1);
+    SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
+    if (entries > 0) {
+        int32_t* sp = P->split.as<int32_t>();
+        SPG_TRY(launch(P, "split_table", [&] { k_split_table<<<grid_for(entries, 256), 256, 0, cs(P)>>>(b, W, chunks, sp); }));
+    }
+    return SPG_OK;
+}
+
+// Reads back (synchronizing) the classification counts of the last
+// symbolic call and nnz(C); the bitmap bin's count sizes the saved bitmaps
+// of the next call with the same operands.
+static spg_status read_counts(spg_plan P, const int64_t* c_row_ptr, int64_t m) {
+    const int64_t* stats = P->stats.as<int64_t>();
+    HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * STATS_WORDS, hipMemcpyDeviceToHost, P->stream));
+    int64_t nnz = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, c_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    std::memcpy(P->num_counts, P->h_stats, sizeof(int64_t) * 4 * NBINS);
+    std::memcpy(P->sym_counts, P->h_stats + STATS_SYM, sizeof(int64_t) * 3 * NBINS);
+    int64_t tot = 0;
+    for (int x = 0; x < NBINS; ++x) tot += P->sym_counts[NBINS + x];
+    P->last_flops = tot;
+    P->last_nnz = nnz;
+    P->num_counts_valid = true;
+    P->bm_sig = P->sig;
+    P->bm_rows = P->sym_counts[BIN_DENSE];
+    return SPG_OK;
+}
+
+// Items of the rank-chunk bin: RC outputs at most (at least one chunk).
+static int32_t rankc_capacity(spg_plan P) {
+    const int32_t W = P->opts.dense_chunk_cols;
+    int32_t RC = std::max(RANKC_CAP, W);
+    while (RC > W && (int64_t)(W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) RC /= 2;
+    return RC;
+}
+
+// Symbolic pass.  The bin kernels locate their rows on the device and stride
+// over them, so a launch is correct for any grid; the grids are sized from
+// the bin counts, read back once the first time these operands are seen and
+// taken from the last call afterwards.  With operands seen before, the whole
+// pass (row analysis, the bins on several streams, the scan, the numeric
+// classification and the numeric pass's preparation) is queued without
+// waiting for the GPU, and the only readback is the final one of the counts
+// and nnz(C), which also checks that no bin skipped as empty gained rows (a
+// structure changed in place: the pass is then redone with fresh counts).
+static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B, int64_t k_lo,
+                                int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz, bool fresh);
+
 extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B,
                                       int64_t k_lo, int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz) {
+    return symbolic_pass(P, sr, A, B, k_lo, k_hi, c_row_ptr, c_nnz, false);
+}
+
+// fresh: read the counts back before the bins even if these operands were
+// seen before
+static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, const spg_csr* B, int64_t k_lo,
+                                int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz, bool fresh) {
     if (P) P->cur = nullptr;
     if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
     if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
@@ -742,129 +835,190 @@ extern "C" spg_status spgemm_symbolic(spg_plan P, spg_semiring sr, const spg_csr
         SPG_TRY(validate_csr(P, B, "B"));
     }
     SPG_TRY(ensure_rows(P, m));
+    P->sig_rows = m;
     Csr a = view(A), b = view(B);
     BinParams bp = bin_params(P, n);
     int64_t* stats = P->stats.as<int64_t>();
-    int32_t* ctr = P->small_i32.as<int32_t>();  // [0] long count, [1..NBINS] cursors
+    int64_t* sstats = stats + STATS_SYM;  // symbolic classification
+    int64_t* nstats = stats;              // numeric classification
+    int32_t* ctr = P->small_i32.as<int32_t>();
     int64_t* cnt = c_row_ptr + 1;
     const int full = (k_lo == 0 && k_hi == A->ncols) ? 1 : 0;
+    int32_t* lists = P->lists.as<int32_t>();
+    const int32_t W = P->opts.dense_chunk_cols;
 
-    SPG_TRY(fill_i64(P, stats, 4 * NBINS + 1, 0));
-    SPG_TRY(fill_i32(P, ctr, 1 + NBINS, 0));
+    SPG_TRY(fill_i64(P, stats, STATS_WORDS, 0));
+    SPG_TRY(fill_i32(P, ctr, SMALL_WORDS, 0));
     RowInfoOut o{P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), P->flops.as<int64_t>(), P->maxb.as<int32_t>(),
-                 P->bin.as<uint8_t>(), cnt, stats, P->long_rows.as<int32_t>(), ctr,
+                 P->bin.as<uint8_t>(), cnt, sstats, P->long_rows.as<int32_t>(), ctr,
                  (unsigned long long*)(stats + 4 * NBINS)};
     if (m > 0) {
         SPG_TRY(launch(P, "rowinfo", [&] {
-            k_rowinfo<<<(unsigned)std::min<int64_t>(grid_for(m, 16), 4096), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
+            k_rowinfo<<<rowinfo_grid(m), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "rowinfo_long", [&] {
             k_rowinfo_long<<<256, 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "bin_scatter", [&] {
-            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), stats, ctr + 1,
-                                                                   P->lists.as<int32_t>());
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), sstats, ctr + CTR_SYM_CURSOR,
+                                                                   lists);
         }));
     }
-    if (!P->frozen) {
-        HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 3 * NBINS, hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipMemcpyAsync(P->h_stats + 3 * NBINS, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
+    Signature sg;
+    sg.a_rp = A->row_ptr; sg.a_col = A->col; sg.b_rp = B->row_ptr; sg.b_col = B->col;
+    sg.m = m; sg.n = n; sg.k = A->ncols; sg.annz = A->nnz; sg.bnnz = B->nnz; sg.k_lo = k_lo; sg.k_hi = k_hi;
+    // The first call with these operands reads back the bitmap bin's row
+    // count (to size the saved bitmaps) and the largest row's products (with
+    // more than 2^19 columns a batch of whole B rows could overflow the
+    // enumerators' int32 counts, so such a row is rejected before any bin
+    // runs).  Later calls with the same operands use the last call's count
+    // and queue everything without waiting.
+    // Bin row counts that size the grids: read back now the first time these
+    // operands are seen (exact), else those of the last call with them
+    // (checked against the real counts at the final readback).  A graph
+    // capture (frozen) reuses the eager call's counts.
+    int64_t hint[NBINS];
+    bool exact = true;
+    const bool known = P->bm_rows >= 0 && P->bm_sig == sg && bp.dense_ok && c_nnz != nullptr && !fresh;
+    if (P->frozen || known) {
+        std::memcpy(hint, P->sym_counts, sizeof(hint));
+        exact = P->frozen;
+    } else if (m > 0) {
+        HIP_TRY(hipMemcpyAsync(P->h_stats, sstats, sizeof(int64_t) * NBINS, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipMemcpyAsync(P->h_stats + NBINS, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
                                P->stream));
         HIP_TRY(hipStreamSynchronize(P->stream));
-        std::memcpy(P->sym_counts, P->h_stats, sizeof(int64_t) * 3 * NBINS);
-        SPG_TRY(check_row_products(bp, P->h_stats[3 * NBINS]));
+        SPG_TRY(check_row_products(bp, P->h_stats[NBINS]));
+        std::memcpy(hint, P->h_stats, sizeof(hint));
+    } else {
+        std::memset(hint, 0, sizeof(hint));
     }
-    int64_t tot = 0;
-    for (int x = 0; x < NBINS; ++x) tot += P->sym_counts[NBINS + x];
-    P->last_flops = tot;
+    const int64_t bitmap_rows = hint[BIN_DENSE];
 
-    // per-bin accumulators, independent bins on separate streams
-    const int32_t* lists = P->lists.as<int32_t>();
-    int64_t bin_off[NBINS + 1];
-    bin_off[0] = 0;
-    for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->sym_counts[x];
-    // the bitmap rows, heaviest first
-    if (P->sym_counts[BIN_DENSE] > 1) SPG_TRY(order_by_work(P, BIN_DENSE, BIN_DENSE + 1, bin_off));
+    // per-bin accumulators: the bitmap rows (heaviest first) on the plan's
+    // stream, the other bins round robin over the helper streams
+    const int nstreams = std::max(1, std::min(P->opts.streams, NAUX + 1));
     SPG_TRY(fork_streams(P));
-    const std::vector<int> sym_order = bins_by_work(P->sym_counts, P->sym_counts + NBINS);
-    StreamLoad sload(P, P->sym_counts);
-    for (size_t oi = 0; oi < sym_order.size(); ++oi) {
-        const int bb = sym_order[oi];
-        const int64_t nr = P->sym_counts[bb];
-        const int32_t* rows = lists + bin_off[bb];
-        if (nr == 0 || bb == BIN_EMPTY || bb == BIN_TINY) continue;
-        use_stream(P, sload, (int)oi, P->sym_counts, bb);
-        if (bb == BIN_SMALL) {
-            SPG_TRY(launch(P, "sym_small", [&] {
-                k_sym_small<<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, P->a_beg.as<int64_t>(),
-                                                                     P->a_end.as<int64_t>(), cnt);
-            }));
-        } else if (bb == BIN_DENSE) {
-            const int32_t nwords = (int32_t)std::min<int64_t>((n + 31) / 32, 1 << 14);
-            uint32_t* save = nullptr;
-            int32_t* hidx = nullptr;
-            int32_t* csave = nullptr;
-            const int32_t W = P->opts.dense_chunk_cols;
-            const int32_t nchunks = (int32_t)((n + W - 1) / W);
-            if (bp.dense_ok && (bp.rank_max_log2 || bp.chunk_counts)) {
-                SPG_TRY(P->heavy_idx.ensure(4 * (size_t)std::max<int64_t>(m, 1), "bitmap slots"));
-                hidx = P->heavy_idx.as<int32_t>();
-            }
-            if (bp.dense_ok && (bp.rank_max_log2 || bp.chunk_counts)) {
-                SPG_TRY(P->bm_save.ensure((size_t)nr * nwords * 4, "row bitmaps"));
-                save = P->bm_save.as<uint32_t>();
-            }
-            if (bp.dense_ok && bp.chunk_counts) {
-                SPG_TRY(P->chunk_save.ensure((size_t)nr * nchunks * 4, "chunk counts"));
+    // the numeric pass's split table (B and W only) on the last helper stream
+    // rank-chunk items are possible (chunk counts recorded); the split table
+    // is needed when a row has more than one chunk
+    const bool chunked = bp.dense_ok && bp.chunk_counts;
+    P->split_ready = false;
+    P->bm_cap = 0;
+    if (chunked && b.ncols > W) {
+        P->cur = nstreams > 1 ? P->aux[nstreams - 2] : P->stream;
+        SPG_TRY(build_split_table(P, b, W));
+        P->split_ready = true;
+    }
+    P->cur = P->stream;
+    if (m > 0 && hint[BIN_DENSE] > 0) SPG_TRY(order_by_work(P, BIN_DENSE, BIN_DENSE + 1, sstats, hint[BIN_DENSE]));
+    if (m > 0) {
+        const int32_t nwords = (int32_t)std::min<int64_t>((n + 31) / 32, 1 << 14);
+        uint32_t* save = nullptr;
+        int32_t* hidx = nullptr;
+        int32_t* csave = nullptr;
+        const int32_t nchunks = (int32_t)((n + W - 1) / W);
+        int64_t slots = 0;
+        if (bp.dense_ok && (bp.rank_max_log2 || bp.chunk_counts)) {
+            // one saved bitmap per row of the bitmap bin, as many as that bin
+            // held in the last call with these operands (bitmap_rows); a row
+            // past the slots is not saved and takes the numeric paths that
+            // need no saved bitmap
+            SPG_TRY(P->heavy_idx.ensure(4 * (size_t)std::max<int64_t>(m, 1), "bitmap slots"));
+            hidx = P->heavy_idx.as<int32_t>();
+            slots = std::min<int64_t>(m, bitmap_rows);
+            SPG_TRY(P->bm_save.ensure((size_t)std::max<int64_t>(slots, 1) * nwords * 4, "row bitmaps"));
+            save = P->bm_save.as<uint32_t>();
+            if (bp.chunk_counts) {
+                SPG_TRY(P->chunk_save.ensure((size_t)std::max<int64_t>(slots, 1) * nchunks * 4, "chunk counts"));
                 csave = P->chunk_save.as<int32_t>();
             }
+        }
+        P->bm_cap = slots;
+        if (hint[BIN_DENSE] > 0) {
+            const BinRef dref{sstats, lists, BIN_DENSE};
             SPG_TRY(with_gm<true>(P, [&](auto gm) {
+                constexpr int GM = decltype(gm)::value;
+                const size_t lds = (size_t)nwords * 4;
                 return launch(P, "sym_bitmap", [&] {
-                    k_sym_bitmap<512, decltype(gm)::value><<<(unsigned)nr, 512, (size_t)nwords * 4, cs(P)>>>(
-                        a, b, rows, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords, save, hidx, csave,
-                        W / 32, nchunks);
+                    k_sym_bitmap<512, GM><<<(unsigned)hint[BIN_DENSE], 512, lds, cs(P)>>>(
+                        a, b, dref, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt, nwords, save, hidx, csave,
+                        W / 32, nchunks, slots);
                 });
             }, true, pipelined(P, b, 4)));
-        } else {
-            SPG_TRY(sym_hash_dispatch(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, rows, nr, cnt));
+        }
+        // the other bins, by decreasing work, round robin over the helper
+        // streams (the bitmap rows keep the plan's stream)
+        std::vector<int> order;
+        for (int bb = BIN_SMALL; bb < BIN_DENSE_PAR; ++bb)
+            if (hint[bb] > 0) order.push_back(bb);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return hint[NBINS + x] + 32 * hint[x] > hint[NBINS + y] + 32 * hint[y];
+        });
+        int k = 0;
+        for (int bb : order) {
+            P->cur = nstreams > 1 ? P->aux[k++ % (nstreams - 1)] : P->stream;
+            if (bb == BIN_SMALL) {
+                SPG_TRY(launch(P, "sym_small", [&] {
+                    k_sym_small<<<grid_for(hint[bb], 4 * SMALL_ROWS), 256, 0, cs(P)>>>(
+                        a, b, BinRef{sstats, lists, BIN_SMALL}, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt);
+                }));
+            } else {
+                SPG_TRY(sym_hash_dispatch(P, HASH_MIN_LOG2 + (bb - BIN_HASH0), a, b, BinRef{sstats, lists, bb},
+                                          hint[bb], cnt));
+            }
         }
     }
     SPG_TRY(join_streams(P));
     SPG_TRY(scan_counts(P, c_row_ptr, m));
 
-    // numeric classification from the exact counts
-    int64_t* nstats = stats + 0;  // reuse: symbolic stats already copied out
-    SPG_TRY(fill_i64(P, nstats, 4 * NBINS, 0));
-    SPG_TRY(fill_i32(P, ctr + 1, NBINS, 0));
+    // numeric classification from the exact counts, and the numeric pass's
+    // preparation: heavy rows ordered by work, the rank-chunk items
     if (m > 0) {
         SPG_TRY(launch(P, "num_classify", [&] {
             k_num_classify<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, c_row_ptr, P->a_beg.as<int64_t>(),
                                                                     P->a_end.as<int64_t>(), P->flops.as<int64_t>(),
-                                                                    bp, P->bin.as<uint8_t>(), nstats);
+                                                                    bp, P->bm_cap > 0 ? P->heavy_idx.as<int32_t>() : nullptr,
+                                                                    P->bin.as<uint8_t>(), nstats);
         }));
         SPG_TRY(launch(P, "bin_scatter", [&] {
-            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), nstats, ctr + 1,
-                                                                   P->lists.as<int32_t>());
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->bin.as<uint8_t>(), nstats, ctr + CTR_NUM_CURSOR,
+                                                                   lists);
         }));
+        // the heavy numeric bins are among the saved bitmap rows
+        const int64_t slots_used = P->bm_cap;
+        if (slots_used > 0) SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, nstats, slots_used));
+        if (chunked && slots_used > 0) {
+            const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
+            SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(
+                                             P->bm_cap * chunks, 1), "rank items"));
+            const int32_t RC = rankc_capacity(P);
+            SPG_TRY(launch(P, "rank_items", [&] {
+                k_rank_items<<<(unsigned)std::min<int64_t>(grid_for(std::max<int64_t>(slots_used, 1), 256), 256), 256, 0,
+                               cs(P)>>>(
+                    BinRef{nstats, lists, BIN_DENSE_PAR}, P->heavy_idx.as<int32_t>(),
+                    P->chunk_save.as<int32_t>(), chunks, RC, P->opts.chunk_group, W, RANK_STATIC_LDS, P->max_lds,
+                    nstats + 3 * NBINS + BIN_DENSE_PAR, P->rank_items.as<RankItem>(), ctr + CTR_RANK_ITEMS);
+            }));
+        }
     }
-    Signature s;
-    s.a_rp = A->row_ptr; s.a_col = A->col; s.b_rp = B->row_ptr; s.b_col = B->col;
-    s.m = m; s.n = n; s.k = A->ncols; s.annz = A->nnz; s.bnnz = B->nnz; s.k_lo = k_lo; s.k_hi = k_hi;
-    P->sig = s;
+    P->sig = sg;
     P->have_symbolic = true;
     if (P->frozen) {
         P->num_counts_valid = true;  // counts of the previous call
         if (c_nnz) *c_nnz = P->last_nnz;
         return SPG_OK;
     }
+    P->last_crp = c_row_ptr;
     if (c_nnz) {
-        HIP_TRY(hipMemcpyAsync(P->h_stats, nstats, sizeof(int64_t) * 4 * NBINS, hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipMemcpyAsync(P->h_stats + 4 * NBINS, c_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipStreamSynchronize(P->stream));
-        std::memcpy(P->num_counts, P->h_stats, sizeof(int64_t) * 4 * NBINS);
-        P->last_nnz = P->h_stats[4 * NBINS];
+        SPG_TRY(read_counts(P, c_row_ptr, m));
+        // a bin skipped as empty by the last call's counts that now holds
+        // rows: the structure behind the same pointers changed; redo with
+        // counts read back first
+        if (!exact)
+            for (int bb = BIN_SMALL; bb <= BIN_DENSE; ++bb)
+                if (hint[bb] == 0 && P->sym_counts[bb] > 0) return symbolic_pass(P, sr, A, B, k_lo, k_hi, c_row_ptr, c_nnz, true);
         *c_nnz = P->last_nnz;
-        P->num_counts_valid = true;
     }
     return SPG_OK;
 }
@@ -897,6 +1051,9 @@ static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int3
     return fail(SPG_ERR_ARG, "bad numeric hash bin");
 }
 
+// Numeric pass: every bin's kernel, launched with the counts the symbolic
+// pass read back (its preparation -- split table, work order, rank-chunk
+// items -- ran inside the symbolic pass).
 template <int SR>
 static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr, int32_t* ccol, void* cval) {
     // output rows start at c_row_ptr, or at P->out_pos for a gathered sub-product
@@ -908,24 +1065,12 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
     int64_t bin_off[NBINS + 1];
     bin_off[0] = 0;
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->num_counts[x];
-    // the split table is built on the caller's stream before the fork
-    bool split_built = false;
-    if ((P->num_counts[BIN_DENSE] || P->num_counts[BIN_DENSE_PAR]) && b.ncols > W) {
-        const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
-        const int64_t entries = b.nrows * (int64_t)(chunks + 1);
-        SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
-        if (entries > 0) {
-            int32_t* sp = P->split.as<int32_t>();
-            SPG_TRY(launch(P, "split_table", [&] {
-                k_split_table<<<grid_for(entries, 256), 256, 0, cs(P)>>>(b, W, chunks, sp);
-            }));
-        }
-        split_built = true;
+    // rows of the column-chunked dense bin need the split table; the
+    // symbolic pass builds it when rank chunks are possible
+    if (P->num_counts[BIN_DENSE] && b.ncols > W && !P->split_ready) {
+        SPG_TRY(build_split_table(P, b, W));
+        P->split_ready = true;
     }
-    // rank-chunk, dense and rank rows (bins 11..15, contiguous), heaviest first
-    if (P->num_counts[BIN_DENSE_PAR] + P->num_counts[BIN_DENSE] + P->num_counts[BIN_RANK0] +
-            P->num_counts[BIN_RANK0 + 1] + P->num_counts[BIN_RANK0 + 2] > 1)
-        SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, bin_off));
     SPG_TRY(fork_streams(P));
     const std::vector<int> num_order = bins_by_work(P->num_counts, P->num_counts + NBINS);
     StreamLoad nload(P, P->num_counts);
@@ -960,33 +1105,19 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
                 });
             }));
         } else if (bb == BIN_DENSE_PAR) {
+            // items (formed in the symbolic pass) of at most RC outputs and G
+            // chunks, G from the same rule as there
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
-            // outputs per item: RANKC_CAP, and at least one whole chunk (<= W
-            // outputs), so every item holds at least one chunk; fewer when the
-            // LDS of the smallest item (one chunk's words + RC values) would
-            // not fit
-            int32_t RC = std::max(RANKC_CAP, W);
-            while (RC > W && (int64_t)(W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) RC /= 2;
-            // chunks per item: about RC outputs at the bin's mean density,
-            // at most chunk_group
-            const double per_chunk = (double)P->num_counts[3 * NBINS + bb] / ((double)nr * chunks);
-            int32_t G = (int32_t)std::lround(per_chunk > 0 ? RC / per_chunk : (double)chunks);
-            G = std::max(1, std::min({G, chunks, P->opts.chunk_group}));
-            while (G > 1 && (int64_t)G * (W / 32) * 8 + (int64_t)RC * 8 + RANK_STATIC_LDS > P->max_lds) --G;
-            SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(nr * chunks, 1), "rank items"));
-            SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
-            int32_t* nitems = P->small_i32.as<int32_t>() + 48;
-            SPG_TRY(fill_i32(P, nitems, 1, 0));
-            RankItem* items = P->rank_items.as<RankItem>();
-            const int32_t* hi = P->heavy_idx.as<int32_t>();
-            SPG_TRY(launch(P, "rank_items", [&] {
-                k_rank_items<<<grid_for(nr, 256), 256, 0, cs(P)>>>(rows, (int32_t)nr, hi, P->chunk_save.as<int32_t>(),
-                                                                 chunks, RC, G, items, nitems);
-            }));
+            const int32_t RC = rankc_capacity(P);
+            const int32_t G = rankc_group(nr, P->num_counts[3 * NBINS + bb], chunks, RC, P->opts.chunk_group, W,
+                                          RANK_STATIC_LDS, P->max_lds);
+            const int32_t* nitems = P->small_i32.as<int32_t>() + CTR_RANK_ITEMS;
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
             const size_t lds = (size_t)G * (W / 32) * 8 + (size_t)RC * sizeof(typename Sr<SR>::acc_t);
             const int32_t* split = chunks > 1 ? P->split.as<int32_t>() : nullptr;
             const unsigned grid = (unsigned)std::min<int64_t>(nr * chunks, 256 * 8);
+            RankItem* items = P->rank_items.as<RankItem>();
+            const int32_t* hi = P->heavy_idx.as<int32_t>();
             SPG_TRY(with_gm_u<true>(P, P->opts.gather_map, P->opts.chunk_unroll, [&](auto gm) {
                 return launch(P, "num_rankc", [&] {
                     k_num_rankc<SR, 512, decltype(gm)::value><<<grid, 512, lds, cs(P)>>>(
@@ -997,21 +1128,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
         } else if (bb == BIN_DENSE) {
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             P->dense_chunks = chunks;
-            const int32_t* split = nullptr;
-            if (chunks > 1) {
-                if (!split_built) {
-                    const int64_t entries = b.nrows * (int64_t)(chunks + 1);
-                    SPG_TRY(P->split.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(entries, 1), "split table"));
-                    if (entries > 0) {
-                        int32_t* sp = P->split.as<int32_t>();
-                        SPG_TRY(launch(P, "split_table", [&] {
-                            k_split_table<<<grid_for(entries, 256), 256, 0, cs(P)>>>(b, W, chunks, sp);
-                        }));
-                    }
-                    split_built = true;
-                }
-                split = P->split.as<int32_t>();
-            }
+            const int32_t* split = chunks > 1 ? P->split.as<int32_t>() : nullptr;
             const unsigned grid = (unsigned)std::min<int64_t>(nr, 1 << 16);
             SPG_TRY(with_gm(P, [&](auto gm) -> spg_status {
                 constexpr int GM = decltype(gm)::value;
@@ -1049,14 +1166,7 @@ extern "C" spg_status spgemm_numeric(spg_plan P, spg_semiring sr, const spg_csr*
     s.m = A->nrows; s.n = B->ncols; s.k = A->ncols; s.annz = A->nnz; s.bnnz = B->nnz; s.k_lo = k_lo; s.k_hi = k_hi;
     if (!P->have_symbolic || !(s == P->sig))
         return fail(SPG_ERR_STATE, "spgemm_numeric needs the matching spgemm_symbolic on this plan first");
-    if (!P->num_counts_valid) {
-        HIP_TRY(hipMemcpyAsync(P->h_stats, P->stats.p, sizeof(int64_t) * 4 * NBINS, hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipMemcpyAsync(P->h_stats + 4 * NBINS, c_row_ptr + s.m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipStreamSynchronize(P->stream));
-        std::memcpy(P->num_counts, P->h_stats, sizeof(int64_t) * 4 * NBINS);
-        P->last_nnz = P->h_stats[4 * NBINS];
-        P->num_counts_valid = true;
-    }
+    if (!P->num_counts_valid) SPG_TRY(read_counts(P, c_row_ptr, s.m));
     if (P->last_nnz > 0 && !c_col) return fail(SPG_ERR_ARG, "c_col is NULL");
     Csr a = view(A), b = view(B);
     switch (sr) {
@@ -1211,6 +1321,8 @@ extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t n
 // ---------------------------------------------------------------------------
 extern "C" spg_status spg_plan_stats(spg_plan P, spg_stats* out) {
     if (!P || !out) return fail(SPG_ERR_ARG, "NULL argument");
+    if (P->have_symbolic && !P->num_counts_valid && !P->frozen && P->last_crp)
+        SPG_TRY(read_counts(P, P->last_crp, P->sig.m));
     std::memset(out, 0, sizeof(*out));
     out->m = P->sig.m;
     out->n = P->sig.n;
@@ -1364,7 +1476,7 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
     bin_off[0] = 0;
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->l_counts[x];
     // the fused bitmap-rank rows (bins 13..15), heaviest first
-    if (bin_off[NBINS] - bin_off[BIN_DENSE_PAR] > 1) SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, bin_off));
+    SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, P->stats.as<int64_t>(), bin_off[NBINS] - bin_off[BIN_DENSE_PAR]));
     SPG_TRY(fork_streams(P));
     const std::vector<int> order = bins_by_work(P->l_counts, P->l_counts + NBINS);
     StreamLoad lload(P, P->l_counts);
@@ -1479,7 +1591,7 @@ extern "C" spg_status spgemm_learned_run(spg_plan P, spg_semiring sr, const spg_
     lp.hash_max_nnz = P->opts.hash_max_nnz;
     if (m > 0) {
         SPG_TRY(launch(P, "rowinfo", [&] {
-            k_rowinfo<<<(unsigned)std::min<int64_t>(grid_for(m, 16), 4096), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
+            k_rowinfo<<<rowinfo_grid(m), 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);
         }));
         SPG_TRY(launch(P, "rowinfo_long", [&] {
             k_rowinfo_long<<<256, 256, 0, cs(P)>>>(a, b, k_lo, k_hi, full, bp, o);

@@ -110,9 +110,8 @@ __device__ inline void wave_locate_rows(const Csr& A, const Csr& B, const int64_
 // row with more than 64 A entries in the window (empty B rows among them)
 // falls back to the one-row search.
 template <class Body>
-__device__ inline void for_small_rows(const Csr& A, const Csr& B, const int32_t* rows, int32_t nrows,
+__device__ inline void for_small_rows(const Csr& A, const Csr& B, const int32_t* rows, int64_t nrows, int64_t w,
                                       const int64_t* a_beg, const int64_t* a_end, Body body) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     int64_t i[SMALL_ROWS], beg[SMALL_ROWS], end[SMALL_ROWS];
     bool ok[SMALL_ROWS];
 #pragma unroll
@@ -144,68 +143,74 @@ __device__ inline void for_small_rows(const Csr& A, const Csr& B, const int32_t*
         if (ok[u]) body(u, i[u], have[u], p[u], q[u]);
 }
 
-// 4 waves per block, SMALL_ROWS rows per wave.
-__global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, const int32_t* rows, int32_t nrows,
-                                                   const int64_t* a_beg, const int64_t* a_end, int64_t* cnt) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w * SMALL_ROWS >= nrows) return;  // whole wave leaves; no block barriers below
+// 4 waves per block, SMALL_ROWS rows per wave, the waves striding over the
+// bin's rows (located on the device).
+__global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, BinRef ref, const int64_t* a_beg,
+                                                   const int64_t* a_end, int64_t* cnt) {
+    const int32_t* rows;
+    int64_t nrows;
+    ref.locate(rows, nrows);
     const int lane = lane_id();
-    uint64_t keys[SMALL_ROWS];
-    int64_t row[SMALL_ROWS];
-    for_small_rows(A, B, rows, nrows, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t, int64_t q) {
-        keys[u] = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
-        row[u] = i;
-    });
+    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * SMALL_ROWS < nrows;
+         w += (int64_t)gridDim.x * 4) {
+        uint64_t keys[SMALL_ROWS];
+        int64_t row[SMALL_ROWS];
+        for_small_rows(A, B, rows, nrows, w, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t, int64_t q) {
+            keys[u] = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
+            row[u] = i;
+        });
 #pragma unroll
-    for (int u = 0; u < SMALL_ROWS; ++u) {
-        if (w * SMALL_ROWS + u >= nrows) break;
-        const uint64_t key = wave_bitonic_sort_u64(keys[u]);
-        const uint64_t prev = lane_prev(key);
-        const bool head = key != ~0ull && (lane == 0 || prev != key);
-        const uint64_t heads = __ballot(head);
-        if (lane == 0) cnt[row[u]] = __popcll(heads);
+        for (int u = 0; u < SMALL_ROWS; ++u) {
+            if (w * SMALL_ROWS + u >= nrows) break;
+            const uint64_t key = wave_bitonic_sort_u64(keys[u]);
+            const uint64_t prev = lane_prev(key);
+            const bool head = key != ~0ull && (lane == 0 || prev != key);
+            const uint64_t heads = __ballot(head);
+            if (lane == 0) cnt[row[u]] = __popcll(heads);
+        }
     }
 }
 
+// Workgroup per row (rows claimed one at a time).
 template <int NT, int LOG2T>
-__global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* rows,
-                                                 const int64_t* a_beg, const int64_t* a_end,
+__global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, BinRef ref, const int64_t* a_beg, const int64_t* a_end,
                                                  int64_t* cnt) {
     constexpr int T = 1 << LOG2T;
     __shared__ int32_t tab[T];
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
-    const int64_t i = rows[blockIdx.x];
-    for (int t = threadIdx.x; t < T; t += NT) tab[t] = EMPTY_KEY;
-    __syncthreads();
-    int32_t mine = 0;
-    for_each_product_u<NT, 4>(
-        a_beg[i], a_end[i], L,
-        [&](int64_t p, int64_t& bs, int32_t& len) {
-            int64_t k = A.col[p];
-            bs = B.rp[k];
-            len = (int32_t)(B.rp[k + 1] - bs);
-        },
-        [&](int, int64_t) {},
-        [&](int64_t q) { return B.col[q]; },
-        [&](int, int32_t j) {
-            uint32_t h = hash_slot(j, LOG2T);
-            while (true) {
-                int32_t cur = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (cur == j) break;
-                if (cur == EMPTY_KEY) {
-                    int32_t old = atomicCAS(&tab[h], EMPTY_KEY, j);
-                    if (old == EMPTY_KEY) {
-                        ++mine;
-                        break;
+    for_each_bin_row(ref, [&](int64_t, int64_t i) {
+        for (int t = threadIdx.x; t < T; t += NT) tab[t] = EMPTY_KEY;
+        __syncthreads();
+        int32_t mine = 0;
+        for_each_product_u<NT, 4>(
+            a_beg[i], a_end[i], L,
+            [&](int64_t p, int64_t& bs, int32_t& len) {
+                int64_t k = A.col[p];
+                bs = B.rp[k];
+                len = (int32_t)(B.rp[k + 1] - bs);
+            },
+            [&](int, int64_t) {},
+            [&](int64_t q) { return B.col[q]; },
+            [&](int, int32_t j) {
+                uint32_t h = hash_slot(j, LOG2T);
+                while (true) {
+                    int32_t cur = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (cur == j) break;
+                    if (cur == EMPTY_KEY) {
+                        int32_t old = atomicCAS(&tab[h], EMPTY_KEY, j);
+                        if (old == EMPTY_KEY) {
+                            ++mine;
+                            break;
+                        }
+                        if (old == j) break;
                     }
-                    if (old == j) break;
+                    h = (h + 1) & (T - 1);
                 }
-                h = (h + 1) & (T - 1);
-            }
-        });
-    int32_t total = block_reduce_add<NT, int32_t>(mine, red);
-    if (threadIdx.x == 0) cnt[i] = total;
+            });
+        int32_t total = block_reduce_add<NT, int32_t>(mine, red);
+        if (threadIdx.x == 0) cnt[i] = total;
+    });
 }
 
 // Dynamic LDS: `nwords` 32-bit bitmap words covering columns [0, n).  Bits
@@ -217,17 +222,18 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, const int32_t* ro
 // that width, each block gathering all of the row's products and keeping
 // those inside it; bitmaps are saved only in the single-block case.
 template <int NT, int GM>
-__global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* rows,
+__global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, BinRef ref,
                                                    const int64_t* a_beg, const int64_t* a_end,
                                                    int64_t* cnt, int32_t nwords, uint32_t* bm_save,
                                                    int32_t* heavy_idx, int32_t* chunk_save,
-                                                   int32_t chunk_words, int32_t nchunks) {
+                                                   int32_t chunk_words, int32_t nchunks, int64_t slots) {
     extern __shared__ uint32_t bm[];
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
     __shared__ int32_t s_chunk[MAX_CHUNKS];
-    const int64_t i = rows[blockIdx.x];
     const int64_t block_cols = (int64_t)nwords * 32;
+    // r: the row's position in the bin list, also its slot among the saved bitmaps
+    for_each_bin_row(ref, [&](int64_t r, int64_t i) {
     if (B.ncols > block_cols) {
         int64_t total = 0;
         for (int64_t cb = 0; cb < B.ncols; cb += block_cols) {
@@ -273,7 +279,9 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
         [&](int64_t q) { return (uint32_t)B.col[q]; },
         [&](int, uint32_t j) { atomicOr(&bm[j >> 5], 1u << (j & 31)); });
     int32_t mine = 0;
-    uint32_t* dst = bm_save ? bm_save + (int64_t)blockIdx.x * nwords : nullptr;
+    // rows past the allocated slots are counted but not saved
+    const bool keep = r < slots;
+    uint32_t* dst = bm_save && keep ? bm_save + r * nwords : nullptr;
     // a wave's 64 consecutive words lie in one chunk (chunk_words is a
     // multiple of 64): the wave sums its counts and adds them once
     for (int t0 = threadIdx.x - lane_id(); t0 < nwords; t0 += NT) {
@@ -282,7 +290,7 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
         const int pc = __popc(w);
         mine += pc;
         if (dst && t < nwords) dst[t] = w;
-        if (chunk_save) {
+        if (chunk_save && keep) {
             const int cs = wave_reduce_add(pc);
             if (lane_id() == 0 && cs) atomicAdd(&s_chunk[t0 / chunk_words], cs);
         }
@@ -290,10 +298,11 @@ __global__ void __launch_bounds__(NT) k_sym_bitmap(Csr A, Csr B, const int32_t* 
     int32_t total = block_reduce_add<NT, int32_t>(mine, red);  // barriers: s_chunk complete
     if (threadIdx.x == 0) {
         cnt[i] = total;
-        if (heavy_idx) heavy_idx[i] = (int32_t)blockIdx.x;
+        if (heavy_idx) heavy_idx[i] = keep ? (int32_t)r : -1;
     }
-    if (chunk_save)
-        for (int c = threadIdx.x; c < nchunks; c += NT) chunk_save[(int64_t)blockIdx.x * nchunks + c] = s_chunk[c];
+    if (chunk_save && keep)
+        for (int c = threadIdx.x; c < nchunks; c += NT) chunk_save[r * nchunks + c] = s_chunk[c];
+    });
 }
 
 }  // namespace spg
