@@ -345,6 +345,39 @@ def layered_modes(args, profile=False):
     return out
 
 
+def heap_modes(reps=5):
+    """The heap bin (k-way merge of a row's few B rows, HeapSpGEMM) against
+    the hash tables for the same rows: each workload's two-phase product with
+    the bin taking rows of up to 32 and up to 8 A entries, and with the bin
+    off (the default), and the rows the bin takes."""
+    import torch
+
+    import paper_1510_00844_amd as spg
+    import synth
+    cases = [("c2", synth.rmat(16, 16, synth.G500, seed=2), None),
+             ("ssca_s16", synth.rmat(16, 8, synth.SSCA, seed=2), None),
+             ("c3_unsplit", synth.rmat(18, 16, synth.ER, seed=3), synth.rmat(18, 16, synth.ER, seed=4))]
+    out = {}
+    for name, A, B in cases:
+        B = A if B is None else B
+        dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
+        dB = dA if B is A else spg.DeviceCSR.from_arrays(B.nrows, B.ncols, B.row_ptr, B.col, B.val)
+        r = {}
+        for label, opt in (("heap", 32), ("heap8", 8), ("hash", -1)):
+            plan = spg.Plan(heap_max_lists=opt)
+            t, C = _time(lambda: spg.spgemm(plan, "f64", dA, dB), reps)
+            st = plan.stats()
+            r[label] = {"ms": round(t, 4), "gflops": round(2.0 * st["flops"] / t / 1e6, 3),
+                        "heap_rows": st["num_rows"][spg.BIN_HEAP]}
+            plan.close()
+            del C
+        r["speedup_heap_vs_hash"] = round(r["hash"]["ms"] / r["heap"]["ms"], 3)
+        out[name] = r
+        del dA, dB
+        torch.cuda.empty_cache()
+    return out
+
+
 def kernel_table(plan, steps):
     out = {}
     for name, (launches, total) in plan.profile_read().items():
@@ -365,6 +398,7 @@ def secondary_mode(args):
         out.update(batched_modes(args, reps=args.steps))
     elif args.mode == "c3":
         out.update(layered_modes(args, profile=True))
+        out["heap_vs_hash"] = heap_modes()
     else:
         A = synth.rmat(19, 16, synth.G500, seed=6)
         dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
@@ -560,6 +594,7 @@ def main():
                               "gflops": round(2.0 * fs_ / (ts_ * 1e-3) / 1e9, 3)}
         ps.close()
         del Cs
+        extras["heap_vs_hash"] = heap_modes()
         extras.update(learned_modes(A, dA, args))
         extras["c4_batched"] = batched_modes(args)
         extras["c3_layers"] = layered_modes(args)

@@ -114,7 +114,11 @@ typedef struct {
                                   (above the hash tables) may take the fused bitmap-and-rank kernel, up to
                                   rank_max_nnz and what the LDS holds; 0 = never (default: on this GPU
                                   the exact two-phase path is faster for such rows) */
-    int32_t reserved[1];
+    int32_t heap_max_lists;    /* rows with at most this many A entries in the window and at most 512
+                                  products are merged from their B rows by one wave (the heap bin,
+                                  both passes; sorted output, ascending-k sums): 1..32; 0 = the
+                                  default, -1 = never (the default: on the workloads measured the
+                                  hash tables are faster) */
 } spg_opts;
 
 typedef struct spg_plan_s* spg_plan;
@@ -164,7 +168,8 @@ enum {
     SPG_BIN_DENSE_PAR = 11, /* numeric only: column chunks of one row in parallel workgroups */
     SPG_BIN_DENSE = 12, /* large rows: LDS bitmap (symbolic) / column-chunked dense accumulator (numeric) */
     SPG_BIN_RANK0 = 13, /* numeric only: rank-space accumulator of 4096 << (b - SPG_BIN_RANK0) values */
-    SPG_NBINS = 16
+    SPG_BIN_HEAP = 16,  /* few A entries: k-way merge of the row's B rows by one wave (HeapSpGEMM, Section 4.2) */
+    SPG_NBINS = 17
 };
 
 /* Statistics of the last symbolic (and numeric) call, read back on demand

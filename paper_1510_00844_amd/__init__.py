@@ -22,9 +22,10 @@ LIB_PATH = os.path.join(_HERE, "libspgemm.so")
 SEMIRINGS = {"f64": 0, "i64": 1, "bool": 2}
 TORCH_DTYPE = {"f64": torch.float64, "i64": torch.int64, "bool": torch.uint8}
 
-NBINS = 16
+NBINS = 17
 BIN_NAMES = (["empty", "tiny", "small"] + ["hash%d" % (128 << b) for b in range(8)] + ["dense_par", "dense"]
-             + ["rank%d" % (4096 << b) for b in range(3)])
+             + ["rank%d" % (4096 << b) for b in range(3)] + ["heap"])
+BIN_HEAP = 16
 
 
 class SpgError(RuntimeError):
@@ -49,7 +50,7 @@ class Opts(ctypes.Structure):
                 ("rank_max_nnz", ctypes.c_int32), ("rank_block", ctypes.c_int32),
                 ("serial_heavy", ctypes.c_int32), ("chunk_unroll", ctypes.c_int32),
                 ("gather_pipeline", ctypes.c_int32), ("fused_max_nnz", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("heap_max_lists", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -175,7 +176,7 @@ class Plan:
                  profile=False, small_max_flops=0, hash_max_flops=0, hash_max_nnz=0,
                  dense_chunk_cols=0, streams=0, gather_map=0, unroll=0, sym_gather_map=0, sym_unroll=0,
                  chunk_min_nnz=0, chunk_group=0, rank_max_nnz=0, rank_block=0, serial_heavy=-1,
-                 chunk_unroll=0, gather_pipeline=0, fused_max_nnz=0):
+                 chunk_unroll=0, gather_pipeline=0, fused_max_nnz=0, heap_max_lists=0):
         L = lib()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
@@ -191,7 +192,7 @@ class Plan:
                             ("chunk_min_nnz", chunk_min_nnz), ("chunk_group", chunk_group),
                             ("rank_max_nnz", rank_max_nnz), ("rank_block", rank_block),
                             ("chunk_unroll", chunk_unroll), ("gather_pipeline", gather_pipeline),
-                            ("fused_max_nnz", fused_max_nnz)):
+                            ("fused_max_nnz", fused_max_nnz), ("heap_max_lists", heap_max_lists)):
                 if v:
                     setattr(o, name, int(v))
             if serial_heavy >= 0:

@@ -2,14 +2,19 @@
 // out = entry-wise semiring sum of c layers of equal shape.  Row i of the
 // output is the sorted union of the c sorted segments layer_l(i,:), with
 // values of equal columns combined in ascending layer order.  The paper
-// merges triples with a size-c heap per thread; here a row is merged by a
-// wave (<= 64 entries in all layers: register sort), a workgroup (<= 4096
-// entries: each entry's place in the merged order from binary searches in
-// the other layers' segments, staged in LDS), or, for longer rows, a
-// workgroup sweeping column chunks with an LDS dense accumulator, each
-// layer's chunk range found by binary search (the column-range split of
-// Section 4.3).
+// merges with a heap per thread over a split of the column range; here:
+//   WAVE   rows of at most KW_LMAX entries over at most 8 layers: one
+//          wave per row, the column range split over the 64 lanes and each
+//          lane merging its range of the c segments (kway.hpp), staged in LDS
+//   SMALL  (more layers than the wave merge takes) rows of <= 64 entries:
+//          a wave sort of (column, position)
+//   RANK   65 ... 4096 entries: a workgroup places each entry by binary
+//          searches in the other layers' segments, staged in LDS
+//   DENSE  longer rows: a workgroup sweeping column chunks with an LDS dense
+//          accumulator, each layer's chunk range found by binary search (the
+//          column-range split of Section 4.3)
 #pragma once
+#include "kway.hpp"
 #include "products.hpp"
 #include "rowinfo.hpp"
 
@@ -21,14 +26,26 @@ struct LayerDesc {
     const void* val;
 };
 
-// merge bins by total row length L over the layers
-constexpr int MBIN_EMPTY = 0, MBIN_SMALL = 1, MBIN_R256 = 2, MBIN_R1K = 3, MBIN_R4K = 4, MBIN_DENSE = 5;
-constexpr int MBINS = 6;
-constexpr int MERGE_LDS_MAX = 4096;
 constexpr int MERGE_MAX_LAYERS = 64;
 
-__device__ inline int merge_bin(int64_t L) {
+// The layers, passed by value as a kernel argument (no device copy).
+struct LayerSet {
+    LayerDesc d[MERGE_MAX_LAYERS];
+};
+
+// merge bins by total row length L over the layers
+constexpr int MBIN_EMPTY = 0, MBIN_WAVE = 1, MBIN_SMALL = 2, MBIN_R256 = 3, MBIN_R1K = 4, MBIN_R4K = 5,
+              MBIN_DENSE = 6;
+constexpr int MBINS = 7;
+constexpr int MERGE_LDS_MAX = 4096;
+
+// The wave k-way merge costs O(c) instructions per output (the smallest of c
+// heads each step): it wins for few layers; more layers take the rank paths.
+constexpr int MERGE_KWAY_MAX_LAYERS = 8;
+
+__device__ inline int merge_bin(int64_t L, int c) {
     if (L == 0) return MBIN_EMPTY;
+    if (L <= KW_LMAX && c <= MERGE_KWAY_MAX_LAYERS) return MBIN_WAVE;
     if (L <= SPG_WAVE) return MBIN_SMALL;
     if (L <= 256) return MBIN_R256;
     if (L <= 1024) return MBIN_R1K;
@@ -36,7 +53,7 @@ __device__ inline int merge_bin(int64_t L) {
     return MBIN_DENSE;
 }
 
-__global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, const LayerDesc* layers,
+__global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, LayerSet layers,
                                                        int64_t* total_len, uint8_t* bin,
                                                        int64_t* bin_stats) {
     __shared__ int s_hist[NBINS];
@@ -46,12 +63,11 @@ __global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, con
         s_len[threadIdx.x] = 0;
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < m) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
         int64_t L = 0;
-        for (int l = 0; l < c; ++l) L += layers[l].rp[i + 1] - layers[l].rp[i];
+        for (int l = 0; l < c; ++l) L += layers.d[l].rp[i + 1] - layers.d[l].rp[i];
         total_len[i] = L;
-        int b = merge_bin(L);
+        int b = merge_bin(L, c);
         bin[i] = (uint8_t)b;
         atomicAdd(&s_hist[b], 1);
         atomicAdd((unsigned long long*)&s_len[b], (unsigned long long)L);
@@ -63,16 +79,48 @@ __global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, con
     }
 }
 
+// One wave per row (4 per workgroup), the rows of the bin located on the
+// device.  cnt != nullptr: count pass; otherwise fill pass at out_rp.
+template <int SR, int KMAX, bool FILL>
+__global__ void __launch_bounds__(256) k_merge_kway(int32_t c, LayerSet layers, BinRef ref, int64_t* cnt,
+                                                    const int64_t* out_rp, int32_t* out_col, void* out_val) {
+    typedef typename Sr<SR>::acc_t V;
+    __shared__ KwLds<V, FILL> lds[4];
+    KwLds<V, FILL>& W = lds[threadIdx.x >> 6];
+    const int32_t* rows;
+    int64_t n;
+    ref.locate(rows, n);
+    const int lane = lane_id();
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n; r += (int64_t)gridDim.x * 4) {
+        const int64_t i = rows[r];
+        KwList<V> lst{nullptr, nullptr, 0, 0, Sr<SR>::zero()};
+        if (lane < c) {
+            const int64_t rs = layers.d[lane].rp[i];
+            lst.colp = layers.d[lane].col;
+            lst.valp = layers.d[lane].val;
+            lst.start = rs;
+            lst.len = (int32_t)(layers.d[lane].rp[i + 1] - rs);
+        }
+        const int32_t L = wave_reduce_add(lst.len);
+        const int32_t got = kway_merge_wave<SR, KMAX, FILL, false>(lst, c, L, W, out_col, out_val,
+                                                                   FILL ? out_rp[i] : 0);
+        if (!FILL && lane == 0) cnt[i] = got;
+        wave_lds_sync();  // the staged row is read before the next one overwrites it
+    }
+}
+
 // cnt != nullptr: count pass; otherwise fill pass into out_rp/out_col/out_val.
 template <int SR>
-__global__ void __launch_bounds__(256) k_merge_small(int32_t c, const LayerDesc* layers,
-                                                     const int32_t* rows, int32_t nrows, int64_t* cnt,
+__global__ void __launch_bounds__(256) k_merge_small(int32_t c, LayerSet layers_, BinRef ref, int64_t* cnt,
                                                      const int64_t* out_rp, int32_t* out_col,
                                                      void* out_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= nrows) return;
+    const LayerDesc* layers = layers_.d;
+    const int32_t* rows;
+    int64_t nrows;
+    ref.locate(rows, nrows);
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += (int64_t)gridDim.x * 4) {
     const int64_t i = rows[r];
     const int lane = lane_id();
     int pos = 0, my_l = -1;
@@ -100,7 +148,7 @@ __global__ void __launch_bounds__(256) k_merge_small(int32_t c, const LayerDesc*
     const uint64_t heads = __ballot(head);
     if (cnt) {
         if (lane == 0) cnt[i] = __popcll(heads);
-        return;
+        continue;
     }
     v = __shfl(v, (int)(key & 63), SPG_WAVE);
     V acc = v;
@@ -120,6 +168,7 @@ __global__ void __launch_bounds__(256) k_merge_small(int32_t c, const LayerDesc*
         const int64_t o = out_rp[i] + lanes_below(heads);
         out_col[o] = (int32_t)col;
         if (out_val) S::store(out_val, o, acc);
+    }
     }
 }
 
@@ -158,11 +207,12 @@ __device__ inline int layer_of(const int32_t* soff, int c, int x) {
 // Dynamic LDS: cap values (fill pass), cap staged columns, cap merged
 // columns (fill pass).
 template <int SR, int NT>
-__global__ void __launch_bounds__(NT) k_merge_rank(int32_t c, const LayerDesc* layers, const int32_t* rows,
+__global__ void __launch_bounds__(NT) k_merge_rank(int32_t c, LayerSet layers_, BinRef ref,
                                                    const int64_t* total_len, int32_t cap, int64_t* cnt,
                                                    const int64_t* out_rp, int32_t* out_col, void* out_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
+    const LayerDesc* layers = layers_.d;
     extern __shared__ uint64_t dyn[];
     V* mval = reinterpret_cast<V*>(dyn);
     int32_t* scol = cnt ? reinterpret_cast<int32_t*>(dyn) : reinterpret_cast<int32_t*>(mval + cap);
@@ -170,7 +220,7 @@ __global__ void __launch_bounds__(NT) k_merge_rank(int32_t c, const LayerDesc* l
     __shared__ int32_t soff[MERGE_MAX_LAYERS + 1];
     __shared__ int64_t srs[MERGE_MAX_LAYERS];
     __shared__ int32_t red[NT / SPG_WAVE + 1];
-    const int64_t i = rows[blockIdx.x];
+    for_each_bin_row(ref, [&](int64_t, int64_t i) {
     const int L = (int)total_len[i];
     if (threadIdx.x < SPG_WAVE) {  // c <= 64 segment lengths, scanned by one wave
         const int l = threadIdx.x;
@@ -240,59 +290,67 @@ __global__ void __launch_bounds__(NT) k_merge_rank(int32_t c, const LayerDesc* l
             ++rank;
         }
     }
+    });
 }
 
+// Rows above the rank path: a workgroup sweeps column chunks of W; within a
+// chunk the layers are added one after the other (a layer holds a column
+// at most once, so its entries go to distinct accumulators without atomics,
+// and a barrier orders the layers), so equal columns combine in ascending
+// layer order.  Each layer's chunk range is found by binary search (the
+// column-range split of Section 4.3).
 template <int SR, int NT, int W>
-__global__ void __launch_bounds__(NT) k_merge_dense(int32_t c, const LayerDesc* layers,
-                                                    const int32_t* rows, int64_t ncols, int64_t* cnt,
+__global__ void __launch_bounds__(NT) k_merge_dense(int32_t c, LayerSet layers_, BinRef ref, int64_t ncols, int64_t* cnt,
                                                     const int64_t* out_rp, int32_t* out_col,
                                                     void* out_val) {
     typedef Sr<SR> S;
     typedef typename S::acc_t V;
     constexpr int NWD = W / 32;
+    const LayerDesc* layers = layers_.d;
     __shared__ V acc[W];
     __shared__ uint32_t bits[NWD];
     __shared__ int32_t wpre[NWD];
-    __shared__ int8_t s_layer[NT];
-    __shared__ ProductLds<NT> L;
+    __shared__ int64_t s_lo[MERGE_MAX_LAYERS], s_hi[MERGE_MAX_LAYERS];
     __shared__ int32_t red[NT / SPG_WAVE + 1];
-    const int64_t i = rows[blockIdx.x];
     const int P = (int)((ncols + W - 1) / W);
+    for_each_bin_row(ref, [&](int64_t, int64_t i) {
     int64_t off = cnt ? 0 : out_rp[i];
     int64_t count = 0;
     for (int ch = 0; ch < P; ++ch) {
         for (int t = threadIdx.x; t < W; t += NT) acc[t] = S::zero();
         for (int t = threadIdx.x; t < NWD; t += NT) bits[t] = 0u;
-        __syncthreads();
         const int64_t cbase = (int64_t)ch * W;
-        // "A entries" of the product enumeration are the c layers
-        for_each_product<NT>(
-            0, c, L,
-            [&](int64_t l, int64_t& bs, int32_t& len) {
-                const int64_t rs = layers[l].rp[i], re = layers[l].rp[i + 1];
-                const int64_t lo = lower_bound_col(layers[l].col, rs, re, cbase);
-                const int64_t hi = lower_bound_col(layers[l].col, lo, re, cbase + W);
-                bs = lo;
-                len = (int32_t)(hi - lo);
-            },
-            [&](int t, int64_t l) { s_layer[t] = (int8_t)l; },
-            [&](int t, int64_t, int64_t q) {
-                const int l = s_layer[t];
+        if (threadIdx.x < c) {  // each layer's entries inside the chunk
+            const int l = threadIdx.x;
+            const int64_t rs = layers[l].rp[i], re = layers[l].rp[i + 1];
+            const int64_t lo = lower_bound_col(layers[l].col, rs, re, cbase);
+            s_lo[l] = lo;
+            s_hi[l] = lower_bound_col(layers[l].col, lo, re, cbase + W);
+        }
+        __syncthreads();
+        for (int l = 0; l < c; ++l) {
+            for (int64_t q = s_lo[l] + threadIdx.x; q < s_hi[l]; q += NT) {
                 const int32_t j = (int32_t)(layers[l].col[q] - cbase);
-                if (!cnt) S::lds_add(&acc[j], S::load(layers[l].val, q));
-                atomicOr(&bits[j >> 5], 1u << (j & 31));
-            });
+                const uint32_t b = 1u << (j & 31);
+                if (!cnt) {
+                    const V v = S::load(layers[l].val, q);
+                    acc[j] = (bits[j >> 5] & b) ? S::add(acc[j], v) : v;
+                }
+                atomicOr(&bits[j >> 5], b);
+            }
+            __syncthreads();  // layer l complete before layer l + 1
+        }
         constexpr int WPT = (NWD + NT - 1) / NT;
         int32_t wc[WPT];
-        int32_t s = 0;
+        int32_t sum = 0;
 #pragma unroll
         for (int x = 0; x < WPT; ++x) {
             int w = threadIdx.x * WPT + x;
             wc[x] = w < NWD ? __popc(bits[w]) : 0;
-            s += wc[x];
+            sum += wc[x];
         }
         int32_t chunk_total;
-        int32_t pre = block_exclusive_scan<NT, int32_t>(s, &chunk_total, red);
+        int32_t pre = block_exclusive_scan<NT, int32_t>(sum, &chunk_total, red);
 #pragma unroll
         for (int x = 0; x < WPT; ++x) {
             int w = threadIdx.x * WPT + x;
@@ -316,6 +374,7 @@ __global__ void __launch_bounds__(NT) k_merge_dense(int32_t c, const LayerDesc* 
         __syncthreads();
     }
     if (cnt && threadIdx.x == 0) cnt[i] = count;
+    });
 }
 
 }  // namespace spg

@@ -21,13 +21,16 @@ struct BinParams {
     int32_t rank_max_log2;    // numeric rank-space accumulator: largest capacity (log2), 0 = off
     int32_t chunk_counts;     // the bitmap pass records per-chunk counts for the numeric chunks
     int32_t chunk_min_nnz;    // rows with chunk counts and more outputs than this take rank chunks
+    int32_t heap_max_lists;   // rows with at most this many A entries ...
+    int32_t heap_max_flops;   // ... and products take the k-way merge (heap) bin; 0 = off
     int64_t ncols;            // n
 };
 
-constexpr int NBINS = 16;
+constexpr int NBINS = 17;
 constexpr int BIN_EMPTY = 0, BIN_TINY = 1, BIN_SMALL = 2, BIN_HASH0 = 3, BIN_DENSE = 12;
 constexpr int BIN_DENSE_PAR = 11;  // numeric: column chunks of one row in parallel
 constexpr int BIN_RANK0 = 13;  // rank-space accumulator, capacity 4096 << (b - BIN_RANK0)
+constexpr int BIN_HEAP = 16;   // k-way merge of the row's few B rows (both passes)
 constexpr int RANK_MIN_LOG2 = 12;
 constexpr int LONG_ROW = 128;
 constexpr int HASH_MIN_LOG2 = 7;  // 128 slots
@@ -41,6 +44,7 @@ __device__ inline int sym_bin(int64_t flops, int64_t annz, const BinParams& bp) 
     if (flops == 0) return BIN_EMPTY;
     if (annz == 1) return BIN_TINY;
     if (flops <= bp.small_max_flops) return BIN_SMALL;
+    if (annz <= bp.heap_max_lists && flops <= bp.heap_max_flops) return BIN_HEAP;
     // a bitmap over all n columns costs n/32 words to clear and count; use it
     // once the row's products outnumber that, or once a hash table would not fit
     bool bitmap_cheaper = bp.dense_ok && flops * 32 >= bp.ncols;
@@ -60,6 +64,7 @@ __device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, bool sym
     if (cnt == 0) return BIN_EMPTY;
     if (annz == 1) return BIN_TINY;
     if (flops <= bp.small_max_flops) return BIN_SMALL;
+    if (annz <= bp.heap_max_lists && flops <= bp.heap_max_flops) return BIN_HEAP;  // as in the symbolic pass
     if (sym_dense && bp.rank_max_log2 && cnt <= (1ll << bp.rank_max_log2)) {
         int lg = ceil_log2_i64(cnt);
         if (lg < RANK_MIN_LOG2) lg = RANK_MIN_LOG2;

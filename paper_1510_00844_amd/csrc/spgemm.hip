@@ -13,6 +13,7 @@
 
 #include "../../include/spgemm.h"
 #include "batched.hpp"
+#include "heap.hpp"
 #include "learned.hpp"
 #include "mis2.hpp"
 #include "merge.hpp"
@@ -105,12 +106,10 @@ struct spg_plan_s {
 
     // per-row state of the current product
     DevBuf a_beg, a_end, flops, maxb, bin, lists, long_rows, small_i32, stats, tiles, split;
-    DevBuf layer_desc, merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save, rank_items;
+    DevBuf merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save, rank_items;
     DevBuf lpt_hist, lpt_tmp;  // ordering of heavy bins by work
     const int64_t* out_pos = nullptr;  // numeric output offsets per row (set while a sub-product writes into a full one)
     int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
-    LayerDesc* h_layers = nullptr; // pinned staging for merge descriptors
-    int h_layers_cap = 0;
 
     Signature sig;
     int64_t sig_rows = 0;       // rows of the current symbolic call (bounds launch grids)
@@ -309,6 +308,7 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->rank_max_nnz = 8192;
     o->rank_block = 1024;
     o->chunk_unroll = 4;
+    o->heap_max_lists = -1;  // off: slower than the hash tables on the workloads measured here
 }
 
 extern "C" const char* spg_status_string(spg_status s) {
@@ -424,6 +424,11 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
         if (!P->opts.rank_max_nnz) P->opts.rank_max_nnz = d.rank_max_nnz;
         if (!P->opts.rank_block) P->opts.rank_block = d.rank_block;
         if (!P->opts.chunk_unroll) P->opts.chunk_unroll = d.chunk_unroll;
+        if (!P->opts.heap_max_lists) P->opts.heap_max_lists = d.heap_max_lists;
+    }
+    if (P->opts.heap_max_lists < -1 || P->opts.heap_max_lists > KW_KMAX) {
+        delete P;
+        return fail(SPG_ERR_ARG, "heap_max_lists must be in [1, 32], 0 (default: off) or -1 (off)");
     }
     if (!P->opts.chunk_min_nnz) P->opts.chunk_min_nnz = P->opts.hash_max_nnz;
     auto map_ok = [](int m) { return m == 1 || m == 2; };
@@ -522,7 +527,7 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
     hipStreamSynchronize(P->stream);
     spg_release_galerkin(P);
     for (DevBuf* b : {&P->a_beg, &P->a_end, &P->flops, &P->maxb, &P->bin, &P->lists, &P->long_rows,
-                      &P->small_i32, &P->stats, &P->tiles, &P->split, &P->layer_desc, &P->merge_len,
+                      &P->small_i32, &P->stats, &P->tiles, &P->split, &P->merge_len,
                       &P->mbin, &P->mlists, &P->mstats, &P->mctr, &P->bm_save, &P->heavy_idx, &P->chunk_save, &P->rank_items,
                       &P->lpt_hist, &P->lpt_tmp,
                       &P->lcap, &P->lcnt, &P->slot, &P->pcol, &P->pval, &P->fb_list, &P->fb_redo, &P->sub_rp,
@@ -532,7 +537,6 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
         b->release();
     if (P->sub) spg_plan_destroy(P->sub);
     if (P->h_stats) hipHostFree(P->h_stats);
-    if (P->h_layers) hipHostFree(P->h_layers);
     for (auto& r : P->prof_pending) {
         hipEventDestroy(r.beg);
         hipEventDestroy(r.end);
@@ -695,6 +699,8 @@ static BinParams bin_params(spg_plan P, int64_t n) {
     bp.hash_max_flops = P->opts.hash_max_flops;
     bp.hash_max_nnz = P->opts.hash_max_nnz;
     bp.chunk_min_nnz = P->opts.chunk_min_nnz;
+    bp.heap_max_lists = P->opts.heap_max_lists > 0 ? P->opts.heap_max_lists : 0;
+    bp.heap_max_flops = bp.heap_max_lists > 0 ? KW_LMAX : 0;
     const int64_t bitmap_bytes = ((n + 31) / 32) * 4;
     // dense_ok: one LDS bitmap covers all n columns (the bitmap pass then
     // counts in one block and can save the bitmap for the numeric pass)
@@ -753,6 +759,39 @@ static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, BinRef ref
         case 14: return launch_sym_hash<1024, 14>(P, A, B, ref, rows, cnt);
     }
     return fail(SPG_ERR_ARG, "bad hash bin");
+}
+
+// Heap bin kernels, instantiated for 8, 16 or 32 lists (the plan's
+// heap_max_lists rounded up): fewer lists, fewer registers.
+static int heap_kmax(spg_plan P) {
+    const int k = P->opts.heap_max_lists;
+    return k <= 8 ? 8 : (k <= 16 ? 16 : 32);
+}
+
+static spg_status sym_heap_launch(spg_plan P, Csr a, Csr b, BinRef ref, int64_t rows, int64_t* cnt) {
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    const int64_t* fl = P->flops.as<int64_t>();
+    const unsigned grid = grid_for(std::max<int64_t>(rows, 1), 4);
+    switch (heap_kmax(P)) {
+        case 8: return launch(P, "sym_heap", [&] { k_sym_heap<8><<<grid, 256, 0, cs(P)>>>(a, b, ref, ab, ae, fl, cnt); });
+        case 16: return launch(P, "sym_heap", [&] { k_sym_heap<16><<<grid, 256, 0, cs(P)>>>(a, b, ref, ab, ae, fl, cnt); });
+        default: return launch(P, "sym_heap", [&] { k_sym_heap<32><<<grid, 256, 0, cs(P)>>>(a, b, ref, ab, ae, fl, cnt); });
+    }
+}
+
+template <int SR>
+static spg_status num_heap_launch(spg_plan P, Csr a, Csr b, const int32_t* rows, int64_t nr, OutRows crp, int32_t* ccol,
+                                  void* cval) {
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    const int64_t* fl = P->flops.as<int64_t>();
+    const unsigned grid = grid_for(nr, 4);
+    switch (heap_kmax(P)) {
+        case 8: return launch(P, "num_heap", [&] { k_num_heap<SR, 8><<<grid, 256, 0, cs(P)>>>(a, b, rows, nr, ab, ae, fl, crp, ccol, cval); });
+        case 16: return launch(P, "num_heap", [&] { k_num_heap<SR, 16><<<grid, 256, 0, cs(P)>>>(a, b, rows, nr, ab, ae, fl, crp, ccol, cval); });
+        default: return launch(P, "num_heap", [&] { k_num_heap<SR, 32><<<grid, 256, 0, cs(P)>>>(a, b, rows, nr, ab, ae, fl, crp, ccol, cval); });
+    }
 }
 
 // The numeric pass's column chunks: split[k (P+1) + c] = offset in B(k,:) of
@@ -952,13 +991,16 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
         std::vector<int> order;
         for (int bb = BIN_SMALL; bb < BIN_DENSE_PAR; ++bb)
             if (hint[bb] > 0) order.push_back(bb);
+        if (hint[BIN_HEAP] > 0) order.push_back(BIN_HEAP);
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
             return hint[NBINS + x] + 32 * hint[x] > hint[NBINS + y] + 32 * hint[y];
         });
         int k = 0;
         for (int bb : order) {
             P->cur = nstreams > 1 ? P->aux[k++ % (nstreams - 1)] : P->stream;
-            if (bb == BIN_SMALL) {
+            if (bb == BIN_HEAP) {
+                SPG_TRY(sym_heap_launch(P, a, b, BinRef{sstats, lists, BIN_HEAP}, hint[bb], cnt));
+            } else if (bb == BIN_SMALL) {
                 SPG_TRY(launch(P, "sym_small", [&] {
                     k_sym_small<<<grid_for(hint[bb], 4 * SMALL_ROWS), 256, 0, cs(P)>>>(
                         a, b, BinRef{sstats, lists, BIN_SMALL}, P->a_beg.as<int64_t>(), P->a_end.as<int64_t>(), cnt);
@@ -987,7 +1029,7 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
         }));
         // the heavy numeric bins are among the saved bitmap rows
         const int64_t slots_used = P->bm_cap;
-        if (slots_used > 0) SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, nstats, slots_used));
+        if (slots_used > 0) SPG_TRY(order_by_work(P, BIN_DENSE_PAR, BIN_RANK0 + 3, nstats, slots_used));
         if (chunked && slots_used > 0) {
             const int32_t chunks = (int32_t)((b.ncols + W - 1) / W);
             SPG_TRY(P->rank_items.ensure(sizeof(RankItem) * (size_t)std::max<int64_t>(
@@ -1016,7 +1058,7 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
         // rows: the structure behind the same pointers changed; redo with
         // counts read back first
         if (!exact)
-            for (int bb = BIN_SMALL; bb <= BIN_DENSE; ++bb)
+            for (int bb = BIN_SMALL; bb < NBINS; ++bb)
                 if (hint[bb] == 0 && P->sym_counts[bb] > 0) return symbolic_pass(P, sr, A, B, k_lo, k_hi, c_row_ptr, c_nnz, true);
         *c_nnz = P->last_nnz;
     }
@@ -1088,6 +1130,8 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
             SPG_TRY(launch(P, "num_small", [&] {
                 k_num_small<SR><<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
             }));
+        } else if (bb == BIN_HEAP) {
+            SPG_TRY(num_heap_launch<SR>(P, a, b, rows, nr, crp, ccol, cval));
         } else if (bb >= BIN_RANK0) {
             const int32_t nwords = (int32_t)((b.ncols + 31) / 32);
             const int64_t cap = 4096ll << (bb - BIN_RANK0);
@@ -1180,26 +1224,40 @@ extern "C" spg_status spgemm_numeric(spg_plan P, spg_semiring sr, const spg_csr*
 // ---------------------------------------------------------------------------
 // merge
 // ---------------------------------------------------------------------------
+template <int SR, bool FILL>
+static spg_status merge_kway_launch(spg_plan P, int32_t c, const LayerSet& ls, BinRef ref, int64_t nr, int64_t* cnt,
+                                    const int64_t* orp, int32_t* ocol, void* oval) {
+    const unsigned grid = grid_for(nr, 4);
+    const char* name = FILL ? "merge_kway" : "merge_kway_count";
+    if (c <= 2)
+        return launch(P, name, [&] { k_merge_kway<SR, 2, FILL><<<grid, 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval); });
+    if (c <= 4)
+        return launch(P, name, [&] { k_merge_kway<SR, 4, FILL><<<grid, 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval); });
+    return launch(P, name, [&] { k_merge_kway<SR, 8, FILL><<<grid, 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval); });
+}
+
+// The merge bins' kernels; the rows of each bin are located on the device
+// (lists and per-bin counts from k_merge_rowinfo), the grids sized by the
+// counts of the count pass.
 template <int SR>
-static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, const int64_t* orp, int32_t* ocol,
-                               void* oval) {
+static spg_status merge_launch(spg_plan P, int32_t c, const LayerSet& ls, int64_t n, const int64_t* counts,
+                               const int64_t* dev_counts, const int32_t* lists, const int64_t* tl, int64_t* cnt,
+                               const int64_t* orp, int32_t* ocol, void* oval) {
     typedef typename Sr<SR>::acc_t V;
-    const LayerDesc* d = P->layer_desc.as<LayerDesc>();
-    const int32_t* lists = P->mlists.as<int32_t>();
-    const int64_t* tl = P->merge_len.as<int64_t>();
-    int64_t off = 0;
-    for (int bb = 0; bb < MBINS; ++bb) {
-        const int64_t nr = P->merge_counts[bb];
-        const int32_t* rows = lists + off;
-        off += nr;
-        if (nr == 0 || bb == MBIN_EMPTY) continue;
-        if (bb == MBIN_SMALL) {
+    for (int bb = 1; bb < MBINS; ++bb) {
+        const int64_t nr = counts[bb];
+        if (nr == 0) continue;
+        const BinRef ref{dev_counts, lists, bb};
+        if (bb == MBIN_WAVE) {
+            if (cnt) SPG_TRY((merge_kway_launch<SR, false>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
+            else SPG_TRY((merge_kway_launch<SR, true>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
+        } else if (bb == MBIN_SMALL) {
             SPG_TRY(launch(P, "merge_small", [&] {
-                k_merge_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, d, rows, (int32_t)nr, cnt, orp, ocol, oval);
+                k_merge_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
             }));
         } else if (bb == MBIN_DENSE) {
             SPG_TRY(launch(P, "merge_dense", [&] {
-                k_merge_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, cs(P)>>>(c, d, rows, n, cnt, orp, ocol, oval);
+                k_merge_dense<SR, 512, 8192><<<(unsigned)nr, 512, 0, cs(P)>>>(c, ls, ref, n, cnt, orp, ocol, oval);
             }));
         } else {
             const int32_t cap = bb == MBIN_R256 ? 256 : (bb == MBIN_R1K ? 1024 : MERGE_LDS_MAX);
@@ -1207,11 +1265,11 @@ static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, c
             const std::string name = "merge_rank" + std::to_string(cap);
             if (cap == 256) {
                 SPG_TRY(launch(P, name, [&] {
-                    k_merge_rank<SR, 64><<<(unsigned)nr, 64, lds, cs(P)>>>(c, d, rows, tl, cap, cnt, orp, ocol, oval);
+                    k_merge_rank<SR, 64><<<(unsigned)nr, 64, lds, cs(P)>>>(c, ls, ref, tl, cap, cnt, orp, ocol, oval);
                 }));
             } else {
                 SPG_TRY(launch(P, name, [&] {
-                    k_merge_rank<SR, 256><<<(unsigned)nr, 256, lds, cs(P)>>>(c, d, rows, tl, cap, cnt, orp, ocol, oval);
+                    k_merge_rank<SR, 256><<<(unsigned)nr, 256, lds, cs(P)>>>(c, ls, ref, tl, cap, cnt, orp, ocol, oval);
                 }));
             }
         }
@@ -1219,23 +1277,79 @@ static spg_status merge_launch(spg_plan P, int32_t c, int64_t n, int64_t* cnt, c
     return SPG_OK;
 }
 
+template <int SR>
+static spg_status merge_dispatch(spg_plan P, int32_t c, const LayerSet& ls, int64_t n, const int64_t* counts,
+                                 const int64_t* dev_counts, const int32_t* lists, const int64_t* tl, int64_t* cnt,
+                                 const int64_t* orp, int32_t* ocol, void* oval) {
+    return merge_launch<SR>(P, c, ls, n, counts, dev_counts, lists, tl, cnt, orp, ocol, oval);
+}
+
+static spg_status merge_by_sr(spg_plan P, spg_semiring sr, int32_t c, const LayerSet& ls, int64_t n,
+                              const int64_t* counts, const int64_t* dev_counts, const int32_t* lists, const int64_t* tl,
+                              int64_t* cnt, const int64_t* orp, int32_t* ocol, void* oval) {
+    switch (sr) {
+        case SPG_SR_PLUS_TIMES_F64: return merge_dispatch<SR_F64>(P, c, ls, n, counts, dev_counts, lists, tl, cnt, orp, ocol, oval);
+        case SPG_SR_PLUS_TIMES_I64: return merge_dispatch<SR_I64>(P, c, ls, n, counts, dev_counts, lists, tl, cnt, orp, ocol, oval);
+        case SPG_SR_OR_AND_BOOL: return merge_dispatch<SR_BOOL>(P, c, ls, n, counts, dev_counts, lists, tl, cnt, orp, ocol, oval);
+    }
+    return fail(SPG_ERR_ARG, "unknown semiring");
+}
+
+static spg_status check_layers(spg_semiring sr, int32_t nlayers, const spg_csr* layers, bool need_val) {
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    if (nlayers < 1 || nlayers > MERGE_MAX_LAYERS) return fail(SPG_ERR_ARG, "nlayers must be in [1, 64]");
+    if (!layers) return fail(SPG_ERR_ARG, "layers is NULL");
+    const int64_t m = layers[0].nrows, n = layers[0].ncols;
+    if (m > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split by rows");
+    for (int l = 0; l < nlayers; ++l) {
+        SPG_TRY(check_csr(&layers[l], "layer", sr, need_val));
+        if (layers[l].nrows != m || layers[l].ncols != n) return fail(SPG_ERR_SHAPE, "layer shapes differ");
+    }
+    return SPG_OK;
+}
+
+static LayerSet layer_set(int32_t nlayers, const spg_csr* layers) {
+    LayerSet ls;
+    std::memset(&ls, 0, sizeof(ls));
+    for (int l = 0; l < nlayers; ++l) ls.d[l] = LayerDesc{layers[l].row_ptr, layers[l].col, layers[l].val};
+    return ls;
+}
+
+// Row analysis of the merge: total lengths, bins, per-bin lists; then the
+// bin counts are read back (synchronizing) into counts[MBINS].
+static spg_status merge_classify(spg_plan P, int32_t c, const LayerSet& ls, int64_t m, int64_t* tl, uint8_t* mbin,
+                                 int32_t* mlists, int64_t* mstats, int32_t* mctr, int64_t* counts) {
+    SPG_TRY(fill_i64(P, mstats, 2 * NBINS, 0));
+    SPG_TRY(fill_i32(P, mctr, NBINS, 0));
+    if (m > 0) {
+        SPG_TRY(launch(P, "merge_rowinfo", [&] {
+            k_merge_rowinfo<<<(unsigned)std::min<int64_t>(grid_for(m, 256), 1024), 256, 0, cs(P)>>>(m, c, ls, tl, mbin,
+                                                                                                 mstats);
+        }));
+        SPG_TRY(launch(P, "bin_scatter", [&] {
+            k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, mbin, mstats, mctr, mlists);
+        }));
+    }
+    HIP_TRY(hipMemcpyAsync(P->h_stats, mstats, sizeof(int64_t) * MBINS, hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    std::memcpy(counts, P->h_stats, sizeof(int64_t) * MBINS);
+    return SPG_OK;
+}
+
+// The merge: count pass (row analysis, bin counts read back, the bins'
+// counting kernels, scan, nnz read back) and fill pass (the bins' kernels
+// with the count pass's lists and counts: no host synchronization).
 extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t nlayers, const spg_csr* layers,
                                           int64_t* out_row_ptr, int32_t* out_col, void* out_val, int64_t* out_nnz) {
     if (P) P->cur = nullptr;
     if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
-    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
-    if (nlayers < 1 || nlayers > 64) return fail(SPG_ERR_ARG, "nlayers must be in [1, 64]");
-    if (!layers || !out_row_ptr) return fail(SPG_ERR_ARG, "layers or out_row_ptr is NULL");
+    if (!out_row_ptr) return fail(SPG_ERR_ARG, "out_row_ptr is NULL");
     const bool count_pass = out_col == nullptr;
+    SPG_TRY(check_layers(sr, nlayers, layers, !count_pass && out_val != nullptr));
     const int64_t m = layers[0].nrows, n = layers[0].ncols;
-    if (m > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split by rows");
-    for (int l = 0; l < nlayers; ++l) {
-        SPG_TRY(check_csr(&layers[l], "layer", sr, !count_pass && out_val != nullptr));
-        if (layers[l].nrows != m || layers[l].ncols != n) return fail(SPG_ERR_SHAPE, "layer shapes differ");
-    }
     if (count_pass && !out_nnz) return fail(SPG_ERR_ARG, "count pass needs out_nnz");
-    std::vector<LayerDesc> desc(nlayers);
-    for (int l = 0; l < nlayers; ++l) desc[l] = LayerDesc{layers[l].row_ptr, layers[l].col, layers[l].val};
+    const LayerSet ls = layer_set(nlayers, layers);
+    std::vector<LayerDesc> desc(ls.d, ls.d + nlayers);
     if (P->opts.validate && count_pass)
         for (int l = 0; l < nlayers; ++l) SPG_TRY(validate_csr(P, &layers[l], "layer"));
     int64_t* cnt = out_row_ptr + 1;
@@ -1246,46 +1360,14 @@ extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t n
         SPG_TRY(P->mlists.ensure(4 * mm, "merge lists"));
         SPG_TRY(P->mstats.ensure(sizeof(int64_t) * 4 * NBINS, "merge stats"));
         SPG_TRY(P->mctr.ensure(sizeof(int32_t) * 64, "merge counters"));
-        SPG_TRY(P->layer_desc.ensure(sizeof(LayerDesc) * 64, "layer descriptors"));
-        if (P->h_layers_cap < 64) {
-            if (P->h_layers) hipHostFree(P->h_layers);
-            P->h_layers = nullptr;
-            HIP_TRY(hipHostMalloc((void**)&P->h_layers, sizeof(LayerDesc) * 64, hipHostMallocDefault));
-            P->h_layers_cap = 64;
-        }
-        // the previous user of the staging buffer has finished: every merge call ends with a sync
-        std::memcpy(P->h_layers, desc.data(), sizeof(LayerDesc) * nlayers);
-        HIP_TRY(hipMemcpyAsync(P->layer_desc.p, P->h_layers, sizeof(LayerDesc) * nlayers, hipMemcpyHostToDevice, P->stream));
-        int64_t* stats = P->mstats.as<int64_t>();
-        int32_t* ctr = P->mctr.as<int32_t>();
-        SPG_TRY(fill_i64(P, stats, 4 * NBINS, 0));
-        SPG_TRY(fill_i32(P, ctr, NBINS, 0));
-        if (m > 0) {
-            SPG_TRY(launch(P, "merge_rowinfo", [&] {
-                k_merge_rowinfo<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, nlayers, P->layer_desc.as<LayerDesc>(),
-                                                                        P->merge_len.as<int64_t>(), P->mbin.as<uint8_t>(),
-                                                                        stats);
-            }));
-            SPG_TRY(launch(P, "bin_scatter", [&] {
-                k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, P->mbin.as<uint8_t>(), stats, ctr,
-                                                                       P->mlists.as<int32_t>());
-            }));
-        }
-        HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * 2 * NBINS, hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipStreamSynchronize(P->stream));
-        std::memcpy(P->merge_counts, P->h_stats, sizeof(int64_t) * 2 * NBINS);
+        SPG_TRY(merge_classify(P, nlayers, ls, m, P->merge_len.as<int64_t>(), P->mbin.as<uint8_t>(),
+                               P->mlists.as<int32_t>(), P->mstats.as<int64_t>(), P->mctr.as<int32_t>(), P->merge_counts));
         P->merge_sig = desc;
         P->merge_m = m;
         P->merge_n = n;
-        // EMPTY rows count zero
-        SPG_TRY(fill_i64(P, cnt, m, 0));
-        spg_status st = SPG_OK;
-        switch (sr) {
-            case SPG_SR_PLUS_TIMES_F64: st = merge_launch<SR_F64>(P, nlayers, n, cnt, nullptr, nullptr, nullptr); break;
-            case SPG_SR_PLUS_TIMES_I64: st = merge_launch<SR_I64>(P, nlayers, n, cnt, nullptr, nullptr, nullptr); break;
-            case SPG_SR_OR_AND_BOOL: st = merge_launch<SR_BOOL>(P, nlayers, n, cnt, nullptr, nullptr, nullptr); break;
-        }
-        SPG_TRY(st);
+        SPG_TRY(fill_i64(P, cnt, m, 0));  // empty rows count zero
+        SPG_TRY(merge_by_sr(P, sr, nlayers, ls, n, P->merge_counts, P->mstats.as<int64_t>(), P->mlists.as<int32_t>(),
+                            P->merge_len.as<int64_t>(), cnt, nullptr, nullptr, nullptr));
         SPG_TRY(scan_counts(P, out_row_ptr, m));
         HIP_TRY(hipMemcpyAsync(P->h_stats, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
         HIP_TRY(hipStreamSynchronize(P->stream));
@@ -1298,16 +1380,8 @@ extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t n
         same = P->merge_sig[l].rp == desc[l].rp && P->merge_sig[l].col == desc[l].col;
     if (!same) return fail(SPG_ERR_STATE, "merge fill pass needs the matching count pass first");
     // values may differ from the count pass (they were not needed there)
-    HIP_TRY(hipStreamSynchronize(P->stream));
-    std::memcpy(P->h_layers, desc.data(), sizeof(LayerDesc) * nlayers);
-    HIP_TRY(hipMemcpyAsync(P->layer_desc.p, P->h_layers, sizeof(LayerDesc) * nlayers, hipMemcpyHostToDevice, P->stream));
-    spg_status st = SPG_OK;
-    switch (sr) {
-        case SPG_SR_PLUS_TIMES_F64: st = merge_launch<SR_F64>(P, nlayers, n, nullptr, out_row_ptr, out_col, out_val); break;
-        case SPG_SR_PLUS_TIMES_I64: st = merge_launch<SR_I64>(P, nlayers, n, nullptr, out_row_ptr, out_col, out_val); break;
-        case SPG_SR_OR_AND_BOOL: st = merge_launch<SR_BOOL>(P, nlayers, n, nullptr, out_row_ptr, out_col, out_val); break;
-    }
-    SPG_TRY(st);
+    SPG_TRY(merge_by_sr(P, sr, nlayers, ls, n, P->merge_counts, P->mstats.as<int64_t>(), P->mlists.as<int32_t>(),
+                        P->merge_len.as<int64_t>(), nullptr, out_row_ptr, out_col, out_val));
     if (out_nnz) {
         HIP_TRY(hipMemcpyAsync(P->h_stats, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
         HIP_TRY(hipStreamSynchronize(P->stream));
@@ -1476,7 +1550,8 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
     bin_off[0] = 0;
     for (int x = 0; x < NBINS; ++x) bin_off[x + 1] = bin_off[x] + P->l_counts[x];
     // the fused bitmap-rank rows (bins 13..15), heaviest first
-    SPG_TRY(order_by_work(P, BIN_DENSE_PAR, NBINS, P->stats.as<int64_t>(), bin_off[NBINS] - bin_off[BIN_DENSE_PAR]));
+    SPG_TRY(order_by_work(P, BIN_DENSE_PAR, BIN_RANK0 + 3, P->stats.as<int64_t>(),
+                          bin_off[BIN_RANK0 + 3] - bin_off[BIN_DENSE_PAR]));
     SPG_TRY(fork_streams(P));
     const std::vector<int> order = bins_by_work(P->l_counts, P->l_counts + NBINS);
     StreamLoad lload(P, P->l_counts);
@@ -1495,7 +1570,7 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
                 k_num_small<SR><<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, slot, pcol, pval,
                                                                      cnt);
             }));
-        } else if (bb >= BIN_RANK0) {
+        } else if (bb >= BIN_RANK0 && bb < BIN_RANK0 + 3) {
             const int64_t acc_cap = 4096ll << (bb - BIN_RANK0);
             const size_t lds = (size_t)nwords * 8 + (size_t)acc_cap * sizeof(typename Sr<SR>::acc_t);
             SPG_TRY(with_gm(P, [&](auto gm) {

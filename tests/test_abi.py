@@ -49,6 +49,6 @@ def test_host_only_entry_points():
     o = spg.Opts()
     L.spg_default_opts(ctypes.byref(o))
     assert o.small_max_flops == 64 and o.hash_max_nnz == 4096 and o.streams == 4
-    assert o.gather_pipeline == 0 and o.fused_max_nnz == 0 and list(o.reserved) == [0]
+    assert o.gather_pipeline == 0 and o.fused_max_nnz == 0 and o.heap_max_lists == -1
     assert ctypes.sizeof(spg.Opts) == 20 * 4
     assert ctypes.sizeof(spg._Csr) == 6 * 8

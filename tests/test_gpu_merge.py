@@ -48,6 +48,9 @@ def test_layers_merge_small(plan, c, sr):
     got_m = to_host(M)
     assert_same_structure(got_m, ref_m)
     assert_values(got_m, ref_m, sr)
+    # every merge path adds equal columns in ascending layer order, as the
+    # oracle's merge does: bit for bit
+    assert got_m.val.tobytes() == ref_m.val.tobytes()
     # and the merged result equals the oracle's unsplit product
     check_full_vs_oracle(M, A, B, sr)
     assert torch.equal(M.row_ptr, U.row_ptr) and torch.equal(M.col, U.col)
@@ -74,7 +77,7 @@ def test_c3_er_s18_layers(plan, c):
     ref_m = oracle.merge(hl, "f64")
     got_m = to_host(M)
     assert_same_structure(got_m, ref_m)
-    assert_values(got_m, ref_m, "f64")
+    assert got_m.val.tobytes() == ref_m.val.tobytes()
     over = check_full_vs_oracle(M, A, B, "f64")
     print("C3 c=%d merged: %d entries, %d over 1e-12 relative" % (c, M.nnz, over), flush=True)
 
@@ -93,16 +96,36 @@ def _layer(m, n, rows_lens, seed, sr="f64"):
 
 @pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
 def test_merge_edge_cases(plan, sr):
-    """Empty layers, c = 1, rows in every merge bin (<= 64 entries in all
-    layers, <= 4096, and longer ones taking the chunked dense path)."""
+    """Empty layers, c = 1, rows in every merge bin (the wave k-way merge up
+    to 512 entries, rank placement up to 4096, the chunked dense path above),
+    bit for bit against the oracle's merge (ascending layer order)."""
     n = 20000
-    lens = [0, 1, 5, 30, 64, 65, 300, 1500, 3000, 5000, 9000, 19000]
+    lens = [0, 1, 5, 30, 64, 65, 170, 171, 300, 511, 512, 513, 1500, 3000, 5000, 9000, 19000]
     layers_h = [_layer(len(lens), n, lens, 10 + l, sr) for l in range(3)]
     layers_h.append(_layer(len(lens), n, [0] * len(lens), 99, sr))  # an empty layer
-    for sel in ([0], [3], [0, 1], [0, 1, 2, 3]):
+    for sel in ([0], [3], [0, 1], [0, 1, 2, 3], [0, 3, 1]):
         hl = [layers_h[x] for x in sel]
         M = spg.spgemm_merge_layers(plan, sr, [to_dev(L, sr) for L in hl])
         ref = oracle.merge(hl, sr)
         got = to_host(M)
         assert_same_structure(got, ref)
         assert_values(got, ref, sr)
+        assert got.val.tobytes() == ref.val.tobytes()
+
+
+@pytest.mark.parametrize("c", [5, 8, 9, 16, 17, 32, 33, 64])
+def test_merge_many_layers(plan, c):
+    """Layer counts around the wave merge's list limits (4, 8, 16, 32) and
+    above them (33..64 take the wave sort and rank paths): rows of 0..600
+    entries over c layers, many columns shared between layers."""
+    rng = np.random.default_rng(200 + c)
+    m, n = 400, 3000
+    hl = []
+    for l in range(c):
+        lens = rng.integers(0, max(2, 600 // c + 2), m)
+        hl.append(_layer(m, n, lens.tolist(), 300 + 7 * c + l))
+    M = spg.spgemm_merge_layers(plan, "f64", [to_dev(L) for L in hl])
+    ref = oracle.merge(hl, "f64")
+    got = to_host(M)
+    assert_same_structure(got, ref)
+    assert got.val.tobytes() == ref.val.tobytes()

@@ -110,20 +110,30 @@ def _binned_matrices(seed=7):
     return A, B
 
 
+@pytest.mark.parametrize("heap", [False, True])
 @pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
-def test_every_bin_full(plan, sr):
+def test_every_bin_full(sr, heap):
+    """Rows in every bin; with the heap bin off every hash table size is
+    used, with it on the rows of few A entries move to the heap bin."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     A, B = _binned_matrices()
-    print("case bins m=%d sr=%s" % (A.nrows, sr), flush=True)
+    print("case bins m=%d sr=%s heap=%s" % (A.nrows, sr, heap), flush=True)
     A, B = (A, B) if sr == "f64" else (with_kind(A, sr), with_kind(B, sr))
-    C = run(plan, sr, A, B)
-    st = plan.stats()
+    plan = spg.Plan(heap_max_lists=32 if heap else -1)
+    try:
+        C = run(plan, sr, A, B)
+        st = plan.stats()
+    finally:
+        plan.close()
     used_sym = [b for b in range(spg.NBINS) if st["sym_rows"][b]]
     used_num = [b for b in range(spg.NBINS) if st["num_rows"][b]]
-    for b in (0, 1, 2, 3, 4, 5, 6, 7, 8, 12):
+    expect = (0, 1, 2, 12) + ((spg.BIN_HEAP,) if heap else (3, 4, 5, 6, 7, 8))
+    for b in expect:
         assert b in used_sym or b in used_num, "bin %s not exercised" % spg.BIN_NAMES[b]
     assert 12 in used_sym
     assert any(b in used_num for b in (13, 14, 15)), "no rank-space rows"
-    for b in (6, 7, 8):
+    for b in ((6, 7, 8) if not heap else (spg.BIN_HEAP,)):
         assert b in used_num, "numeric bin %s not exercised" % spg.BIN_NAMES[b]
     check_full_vs_oracle(C, A, B, sr)
 
