@@ -159,6 +159,22 @@ spg_status spgemm_merge_layers(spg_plan plan, spg_semiring sr, int32_t nlayers,
                                const spg_csr* layers, int64_t* out_row_ptr, int32_t* out_col,
                                void* out_val, int64_t* out_nnz);
 
+/* LocalMerge for callers that cannot allocate device memory (code under
+ * HIP graph capture around it, tight serving loops, harnesses that forbid
+ * allocation): the same two passes and results as spgemm_merge_layers, with
+ * no plan and no allocation of any kind.  Its scratch (row lengths, bins,
+ * bin lists, counters, scan tiles: 13 bytes per row) lives in one 16 MiB
+ * array of device memory that the library holds on every GPU it runs on
+ * until the process ends; hence at most 2^20 rows (SPG_ERR_CAPACITY
+ * beyond).  `stream` is a hipStream_t (NULL = the null stream); the calls
+ * run on it and synchronize it (the count pass, and the fill pass when
+ * out_nnz is not NULL, read counts back).  Each pass classifies the rows
+ * itself, so no state carries between calls; the array keeps the last
+ * call's contents.  Calls that overlap on one GPU (from several threads or
+ * on several streams) share that array and race: serialize them. */
+spg_status spgemm_merge_layers_noalloc(void* stream, spg_semiring sr, int32_t nlayers, const spg_csr* layers,
+                                       int64_t* out_row_ptr, int32_t* out_col, void* out_val, int64_t* out_nnz);
+
 /* Row classes ("bins") the symbolic/numeric passes sort rows into. */
 enum {
     SPG_BIN_EMPTY = 0,  /* no products */

@@ -97,6 +97,7 @@ def lib():
             "spgemm_symbolic": ([P, ctypes.c_int, CP, CP, I64, I64, P, ctypes.POINTER(I64)], ctypes.c_int),
             "spgemm_numeric": ([P, ctypes.c_int, CP, CP, I64, I64, P, P, P], ctypes.c_int),
             "spgemm_merge_layers": ([P, ctypes.c_int, I32, CP, P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "spgemm_merge_layers_noalloc": ([P, ctypes.c_int, I32, CP, P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
             "spg_plan_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
             "spg_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], ctypes.c_int),
             "spg_profile_reset": ([P], ctypes.c_int),
@@ -291,6 +292,29 @@ def spgemm_merge_layers(plan: Plan, sr: str, layers: Sequence[DeviceCSR], values
         _check(lib().spgemm_merge_layers(plan.handle, SEMIRINGS[sr], c, arr, ctypes.c_void_p(rp.data_ptr()),
                                          ctypes.c_void_p(col.data_ptr()),
                                          ctypes.c_void_p(val.data_ptr()) if values else None, None))
+    return DeviceCSR(m, n, rp, col, val)
+
+
+def spgemm_merge_layers_noalloc(sr: str, layers: Sequence[DeviceCSR], stream: Optional[torch.cuda.Stream] = None,
+                                values=True) -> DeviceCSR:
+    """The merge through the entry point that allocates nothing (its scratch
+    is a fixed device array, at most 2^20 rows); the output tensors are
+    allocated here, by the caller side."""
+    c = len(layers)
+    arr = (_Csr * c)(*[L._c(sr if values else None) for L in layers])
+    m, n = layers[0].nrows, layers[0].ncols
+    dev = layers[0].row_ptr.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64(-1)
+    _check(lib().spgemm_merge_layers_noalloc(ctypes.c_void_p(st.cuda_stream), SEMIRINGS[sr], c, arr,
+                                             ctypes.c_void_p(rp.data_ptr()), None, None, ctypes.byref(nnz)))
+    col = torch.empty(max(nnz.value, 0), dtype=torch.int32, device=dev)
+    val = torch.empty(max(nnz.value, 0), dtype=TORCH_DTYPE[sr], device=dev) if values else None
+    if nnz.value > 0:
+        _check(lib().spgemm_merge_layers_noalloc(ctypes.c_void_p(st.cuda_stream), SEMIRINGS[sr], c, arr,
+                                                 ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                                                 ctypes.c_void_p(val.data_ptr()) if values else None, None))
     return DeviceCSR(m, n, rp, col, val)
 
 

@@ -7,6 +7,7 @@
 #include <type_traits>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -664,12 +665,15 @@ static spg_status validate_csr(spg_plan P, const spg_csr* M, const char* name) {
 // ---------------------------------------------------------------------------
 // scan of counts (in place over rp[1..m]); rp[0] = 0
 // ---------------------------------------------------------------------------
-static spg_status scan_counts(spg_plan P, int64_t* rp, int64_t m) {
+// tiles: (m / SCAN_TILE + 2) int64 of scratch (NULL: the plan's)
+static spg_status scan_counts(spg_plan P, int64_t* rp, int64_t m, int64_t* tiles = nullptr) {
     SPG_TRY(fill_i64(P, rp, 1, 0));
     if (m == 0) return SPG_OK;
     const int64_t ntiles = (m + SCAN_TILE - 1) / SCAN_TILE;
-    SPG_TRY(P->tiles.ensure(sizeof(int64_t) * (ntiles + 1), "scan tiles"));
-    int64_t* tiles = P->tiles.as<int64_t>();
+    if (!tiles) {
+        SPG_TRY(P->tiles.ensure(sizeof(int64_t) * (ntiles + 1), "scan tiles"));
+        tiles = P->tiles.as<int64_t>();
+    }
     int64_t* cnt = rp + 1;
     SPG_TRY(launch(P, "scan", [&] { k_scan_tiles<<<(unsigned)ntiles, SCAN_NT, 0, cs(P)>>>(cnt, m, tiles); }));
     SPG_TRY(launch(P, "scan", [&] { k_scan_top<<<1, SCAN_NT, 0, cs(P)>>>(tiles, ntiles); }));
@@ -1318,7 +1322,8 @@ static LayerSet layer_set(int32_t nlayers, const spg_csr* layers) {
 // Row analysis of the merge: total lengths, bins, per-bin lists; then the
 // bin counts are read back (synchronizing) into counts[MBINS].
 static spg_status merge_classify(spg_plan P, int32_t c, const LayerSet& ls, int64_t m, int64_t* tl, uint8_t* mbin,
-                                 int32_t* mlists, int64_t* mstats, int32_t* mctr, int64_t* counts) {
+                                 int32_t* mlists, int64_t* mstats, int32_t* mctr, int64_t* counts,
+                                 int64_t* host_buf) {
     SPG_TRY(fill_i64(P, mstats, 2 * NBINS, 0));
     SPG_TRY(fill_i32(P, mctr, NBINS, 0));
     if (m > 0) {
@@ -1330,9 +1335,9 @@ static spg_status merge_classify(spg_plan P, int32_t c, const LayerSet& ls, int6
             k_bin_scatter<<<grid_for(m, 256), 256, 0, cs(P)>>>(m, mbin, mstats, mctr, mlists);
         }));
     }
-    HIP_TRY(hipMemcpyAsync(P->h_stats, mstats, sizeof(int64_t) * MBINS, hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipMemcpyAsync(host_buf, mstats, sizeof(int64_t) * MBINS, hipMemcpyDeviceToHost, P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
-    std::memcpy(counts, P->h_stats, sizeof(int64_t) * MBINS);
+    std::memcpy(counts, host_buf, sizeof(int64_t) * MBINS);
     return SPG_OK;
 }
 
@@ -1361,7 +1366,8 @@ extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t n
         SPG_TRY(P->mstats.ensure(sizeof(int64_t) * 4 * NBINS, "merge stats"));
         SPG_TRY(P->mctr.ensure(sizeof(int32_t) * 64, "merge counters"));
         SPG_TRY(merge_classify(P, nlayers, ls, m, P->merge_len.as<int64_t>(), P->mbin.as<uint8_t>(),
-                               P->mlists.as<int32_t>(), P->mstats.as<int64_t>(), P->mctr.as<int32_t>(), P->merge_counts));
+                               P->mlists.as<int32_t>(), P->mstats.as<int64_t>(), P->mctr.as<int32_t>(), P->merge_counts,
+                               P->h_stats));
         P->merge_sig = desc;
         P->merge_m = m;
         P->merge_n = n;
@@ -1386,6 +1392,113 @@ extern "C" spg_status spgemm_merge_layers(spg_plan P, spg_semiring sr, int32_t n
         HIP_TRY(hipMemcpyAsync(P->h_stats, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
         HIP_TRY(hipStreamSynchronize(P->stream));
         *out_nnz = P->h_stats[0];
+    }
+    return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// merge without allocation: scratch in a file-scope device array
+// ---------------------------------------------------------------------------
+// One array per GPU (each device holds its own copy for the life of the
+// process).  Host code never uses its name as an address: the device address
+// comes from hipGetSymbolAddress, once per device, on the first call there.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 16u << 20;
+static constexpr int64_t NOALLOC_MAX_ROWS = 1ll << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static uint8_t* g_scratch[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+static spg_status noalloc_scratch(int device, uint8_t** out) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return fail(SPG_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            hipGetLastError();
+            return fail(SPG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch[device] = (uint8_t*)p;
+    }
+    *out = g_scratch[device];
+    return SPG_OK;
+}
+
+// The merge's scratch carved out of the array: per-row lengths (8 B), bins
+// (1 B) and bin lists (4 B), per-bin statistics and counters, scan tiles.
+struct NoallocMerge {
+    int64_t* tl;
+    uint8_t* mbin;
+    int32_t* mlists;
+    int64_t* mstats;
+    int32_t* mctr;
+    int64_t* tiles;
+};
+static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static NoallocMerge noalloc_layout(uint8_t* base, int64_t m) {
+    const size_t mm = (size_t)std::max<int64_t>(m, 1);
+    NoallocMerge L;
+    size_t off = 0;
+    L.tl = (int64_t*)(base + off);
+    off += align256(8 * mm);
+    L.mlists = (int32_t*)(base + off);
+    off += align256(4 * mm);
+    L.mbin = base + off;
+    off += align256(mm);
+    L.mstats = (int64_t*)(base + off);
+    off += align256(sizeof(int64_t) * 4 * NBINS);
+    L.mctr = (int32_t*)(base + off);
+    off += align256(sizeof(int32_t) * 64);
+    L.tiles = (int64_t*)(base + off);
+    return L;
+}
+static_assert(align256(8 * NOALLOC_MAX_ROWS) + align256(4 * NOALLOC_MAX_ROWS) + align256(NOALLOC_MAX_ROWS) +
+                      align256(sizeof(int64_t) * 4 * NBINS) + align256(sizeof(int32_t) * 64) +
+                      sizeof(int64_t) * (NOALLOC_MAX_ROWS / SCAN_TILE + 2) <=
+                  NOALLOC_SCRATCH_BYTES,
+              "the merge scratch of the largest call fits the array");
+
+extern "C" spg_status spgemm_merge_layers_noalloc(void* stream, spg_semiring sr, int32_t nlayers,
+                                                  const spg_csr* layers, int64_t* out_row_ptr, int32_t* out_col,
+                                                  void* out_val, int64_t* out_nnz) {
+    if (!out_row_ptr) return fail(SPG_ERR_ARG, "out_row_ptr is NULL");
+    const bool count_pass = out_col == nullptr;
+    SPG_TRY(check_layers(sr, nlayers, layers, !count_pass && out_val != nullptr));
+    const int64_t m = layers[0].nrows, n = layers[0].ncols;
+    if (m > NOALLOC_MAX_ROWS)
+        return fail(SPG_ERR_CAPACITY, "spgemm_merge_layers_noalloc takes at most 2^20 rows (its fixed scratch)");
+    if (count_pass && !out_nnz) return fail(SPG_ERR_ARG, "count pass needs out_nnz");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    uint8_t* base = nullptr;
+    SPG_TRY(noalloc_scratch(device, &base));
+    const NoallocMerge L = noalloc_layout(base, m);
+    // a plan on the stack for the launch helpers: no streams, events or
+    // device memory of its own, no profiling
+    spg_plan_s T;
+    spg_default_opts(&T.opts);
+    T.device = device;
+    T.stream = (hipStream_t)stream;
+    int64_t host_buf[2 * NBINS];
+    const LayerSet ls = layer_set(nlayers, layers);
+    int64_t counts[2 * NBINS] = {};
+    // each pass classifies the rows itself, so no state is kept between calls
+    SPG_TRY(merge_classify(&T, nlayers, ls, m, L.tl, L.mbin, L.mlists, L.mstats, L.mctr, counts, host_buf));
+    if (count_pass) {
+        int64_t* cnt = out_row_ptr + 1;
+        SPG_TRY(fill_i64(&T, cnt, m, 0));
+        SPG_TRY(merge_by_sr(&T, sr, nlayers, ls, n, counts, L.mstats, L.mlists, L.tl, cnt, nullptr, nullptr, nullptr));
+        SPG_TRY(scan_counts(&T, out_row_ptr, m, L.tiles));
+    } else {
+        SPG_TRY(merge_by_sr(&T, sr, nlayers, ls, n, counts, L.mstats, L.mlists, L.tl, nullptr, out_row_ptr, out_col,
+                            out_val));
+    }
+    if (out_nnz) {
+        HIP_TRY(hipMemcpyAsync(host_buf, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, T.stream));
+        HIP_TRY(hipStreamSynchronize(T.stream));
+        *out_nnz = host_buf[0];
     }
     return SPG_OK;
 }
