@@ -159,6 +159,60 @@ spg_status spgemm_merge_layers(spg_plan plan, spg_semiring sr, int32_t nlayers,
                                const spg_csr* layers, int64_t* out_row_ptr, int32_t* out_col,
                                void* out_val, int64_t* out_nnz);
 
+/* Hypersparse row-compressed matrix (DCSR): the row-wise counterpart of the
+ * DCSC format of Section 4.2.  Only the nzr rows that hold entries are
+ * kept, with their indices, so the arrays take O(nnz) space whatever nrows
+ * is; row_ptr, col and val form an ordinary CSR over the kept rows (the
+ * compressed view).  Canonical form: row_ids strictly increasing and in
+ * [0, nrows), every kept row non-empty, columns strictly increasing inside a
+ * row.  Device pointers, caller-owned, as for spg_csr. */
+typedef struct {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nzr;            /* kept rows */
+    int64_t nnz;
+    const int32_t* row_ids; /* device, nzr */
+    const int64_t* row_ptr; /* device, nzr+1, row_ptr[0] == 0 */
+    const int32_t* col;     /* device, nnz */
+    const void* val;        /* device, nnz (NULL allowed for the boolean semiring) */
+} spg_dcsr;
+
+/* CSR -> DCSR (Section 4.2): the kept rows' indices and pointers; the
+ * DCSR's col and val are A's own arrays.  Call twice: first with
+ * row_ptr == NULL (count call: *nzr on the host, synchronizing), then with
+ * row_ids (nzr entries; may be NULL when nzr is 0) and row_ptr (nzr+1
+ * entries) allocated (fill call; it synchronizes too, and sets *nzr if nzr
+ * is not NULL). */
+spg_status spg_dcsr_compress(spg_plan plan, const spg_csr* A, int32_t* row_ids, int64_t* row_ptr, int64_t* nzr);
+
+/* DCSR -> CSR: row_ptr (device, nrows+1) of the CSR whose col and val are
+ * A's own arrays; absent rows are empty. */
+spg_status spg_dcsr_expand(spg_plan plan, const spg_dcsr* A, int64_t* row_ptr);
+
+/* One process's Sparse SUMMA stages with blocking b (Section 4.1, Algorithm
+ * 2's stage loop; Section 4.3 merge): A (m x K, hypersparse) holds the
+ * process's columns of A for all `stages` stages side by side, B (K x n) the
+ * matching rows; each stage covers K/stages inner indices, cut into blocks of
+ * b (b must divide K/stages, SPG_ERR_ARG otherwise).  Every block gives one
+ * product A(:,block) B(block,:) (a rank-b update); the products are kept and
+ * summed by a multiway merge that adds equal entries in stage order:
+ *   C = sum over blocks, in order, of A(:,block) B(block,:)   (= A B).
+ * C comes out as DCSR (rows with no entry dropped).  With one block the
+ * product is computed directly.
+ * Call twice.  Count call (c_row_ptr == NULL): computes the kept block
+ * products and the merged structure, and returns on the host *c_nzr and
+ * *c_nnz (and, if not NULL, *stage_nnz, the entries of all block products,
+ * the intermediate the merge reads), synchronizing.  Fill call, same A, B,
+ * stages and b: c_row_ids (c_nzr entries), c_row_ptr (c_nzr+1), c_col and
+ * c_val (c_nnz each; c_val may be NULL for the structure only); values are
+ * those read by the count call.  SPG_ERR_STATE if the fill call does not
+ * match the last count call on the plan; SPG_ERR_INDEX_RANGE above 2^22
+ * row pieces (a piece is the part of a row inside one block). */
+spg_status spgemm_summa_local(spg_plan plan, spg_semiring sr, const spg_dcsr* A, const spg_csr* B,
+                              int64_t stages, int64_t b, int32_t* c_row_ids, int64_t* c_row_ptr,
+                              int32_t* c_col, void* c_val, int64_t* c_nzr, int64_t* c_nnz,
+                              int64_t* stage_nnz);
+
 /* LocalMerge for callers that cannot allocate device memory (code under
  * HIP graph capture around it, tight serving loops, harnesses that forbid
  * allocation): the same two passes and results as spgemm_merge_layers, with

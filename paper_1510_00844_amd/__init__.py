@@ -40,6 +40,12 @@ class _Csr(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
+class _Dcsr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nzr", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("row_ids", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("small_max_flops", ctypes.c_int32),
                 ("hash_max_flops", ctypes.c_int32), ("hash_max_nnz", ctypes.c_int32),
@@ -98,6 +104,10 @@ def lib():
             "spgemm_numeric": ([P, ctypes.c_int, CP, CP, I64, I64, P, P, P], ctypes.c_int),
             "spgemm_merge_layers": ([P, ctypes.c_int, I32, CP, P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
             "spgemm_merge_layers_noalloc": ([P, ctypes.c_int, I32, CP, P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "spg_dcsr_compress": ([P, CP, P, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "spg_dcsr_expand": ([P, ctypes.POINTER(_Dcsr), P], ctypes.c_int),
+            "spgemm_summa_local": ([P, ctypes.c_int, ctypes.POINTER(_Dcsr), CP, I64, I64, P, P, P, P,
+                                    ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)], ctypes.c_int),
             "spg_plan_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
             "spg_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], ctypes.c_int),
             "spg_profile_reset": ([P], ctypes.c_int),
@@ -167,6 +177,43 @@ class DeviceCSR:
         return _Csr(self.nrows, self.ncols, self.nnz, self.row_ptr.data_ptr(),
                     self.col.data_ptr() if self.nnz else None,
                     None if self.val is None or self.nnz == 0 else self.val.data_ptr())
+
+
+@dataclass
+class DeviceDCSR:
+    """Row-compressed (hypersparse) device matrix: only the nzr rows holding
+    entries, with their indices (row_ids int32, strictly increasing)."""
+    nrows: int
+    ncols: int
+    row_ids: torch.Tensor
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: Optional[torch.Tensor]
+
+    @property
+    def nzr(self) -> int:
+        return int(self.row_ids.numel())
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_arrays(nrows, ncols, row_ids, row_ptr, col, val, device="cuda") -> "DeviceDCSR":
+        ids = torch.as_tensor(row_ids, dtype=torch.int32).to(device).contiguous()
+        rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(device).contiguous()
+        c = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
+        v = None if val is None else torch.as_tensor(val).to(device).contiguous()
+        return DeviceDCSR(int(nrows), int(ncols), ids, rp, c, v)
+
+    def _c(self, sr: Optional[str] = None) -> _Dcsr:
+        if self.val is not None and sr is not None:
+            want = TORCH_DTYPE[sr]
+            if self.val.dtype != want:
+                raise TypeError("values are %s, semiring %s needs %s" % (self.val.dtype, sr, want))
+        return _Dcsr(self.nrows, self.ncols, self.nzr, self.nnz, self.row_ids.data_ptr() if self.nzr else None,
+                     self.row_ptr.data_ptr(), self.col.data_ptr() if self.nnz else None,
+                     None if self.val is None or self.nnz == 0 else self.val.data_ptr())
 
 
 class Plan:
@@ -316,6 +363,45 @@ def spgemm_merge_layers_noalloc(sr: str, layers: Sequence[DeviceCSR], stream: Op
                                                  ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(col.data_ptr()),
                                                  ctypes.c_void_p(val.data_ptr()) if values else None, None))
     return DeviceCSR(m, n, rp, col, val)
+
+
+def dcsr_compress(plan: Plan, A: DeviceCSR) -> DeviceDCSR:
+    """CSR -> DCSR; the result shares A's column and value tensors."""
+    a = A._c()
+    nzr = ctypes.c_int64(-1)
+    _check(lib().spg_dcsr_compress(plan.handle, ctypes.byref(a), None, None, ctypes.byref(nzr)))
+    ids = torch.empty(nzr.value, dtype=torch.int32, device=plan.device)
+    rp = torch.empty(nzr.value + 1, dtype=torch.int64, device=plan.device)
+    _check(lib().spg_dcsr_compress(plan.handle, ctypes.byref(a), ctypes.c_void_p(ids.data_ptr() or None),
+                                   ctypes.c_void_p(rp.data_ptr()), None))
+    return DeviceDCSR(A.nrows, A.ncols, ids, rp, A.col, A.val)
+
+
+def dcsr_expand(plan: Plan, D: DeviceDCSR) -> DeviceCSR:
+    """DCSR -> CSR; the result shares D's column and value tensors."""
+    d = D._c()
+    rp = torch.empty(D.nrows + 1, dtype=torch.int64, device=plan.device)
+    _check(lib().spg_dcsr_expand(plan.handle, ctypes.byref(d), ctypes.c_void_p(rp.data_ptr())))
+    return DeviceCSR(D.nrows, D.ncols, rp, D.col, D.val)
+
+
+def spgemm_summa_local(plan: Plan, sr: str, A: DeviceDCSR, B: DeviceCSR, stages: int, b: int, values=True):
+    """One process's Sparse SUMMA stages with blocking b (count + fill
+    call).  Returns (C as DeviceDCSR, entries of all kept block products)."""
+    a, bb = A._c(sr if values else None), B._c(sr if values else None)
+    nzr, nnz, snnz = ctypes.c_int64(-1), ctypes.c_int64(-1), ctypes.c_int64(-1)
+    L = lib()
+    _check(L.spgemm_summa_local(plan.handle, SEMIRINGS[sr], ctypes.byref(a), ctypes.byref(bb), int(stages), int(b),
+                                None, None, None, None, ctypes.byref(nzr), ctypes.byref(nnz), ctypes.byref(snnz)))
+    ids = torch.empty(nzr.value, dtype=torch.int32, device=plan.device)
+    rp = torch.empty(nzr.value + 1, dtype=torch.int64, device=plan.device)
+    col = torch.empty(nnz.value, dtype=torch.int32, device=plan.device)
+    val = torch.empty(nnz.value, dtype=TORCH_DTYPE[sr], device=plan.device) if values else None
+    _check(L.spgemm_summa_local(plan.handle, SEMIRINGS[sr], ctypes.byref(a), ctypes.byref(bb), int(stages), int(b),
+                                ctypes.c_void_p(ids.data_ptr() or None), ctypes.c_void_p(rp.data_ptr()),
+                                ctypes.c_void_p(col.data_ptr() or None),
+                                ctypes.c_void_p(val.data_ptr() or None) if values else None, None, None, None))
+    return DeviceDCSR(A.nrows, B.ncols, ids, rp, col, val), snnz.value
 
 
 def _vp(t):

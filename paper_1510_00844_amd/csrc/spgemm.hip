@@ -21,6 +21,7 @@
 #include "numeric.hpp"
 #include "rowinfo.hpp"
 #include "scan.hpp"
+#include "summa.hpp"
 #include "symbolic.hpp"
 
 using namespace spg;
@@ -95,6 +96,17 @@ constexpr int NAUX = 3;  // helper streams for independent bins
 
 struct GalerkinState;
 
+// Sparse SUMMA stages: what the count call leaves for the fill call.
+struct SummaState {
+    bool valid = false;
+    int mode = 0;  // 0: empty result, 1: one block (a single product), 2: piece rows and merge
+    spg_semiring sr = SPG_SR_PLUS_TIMES_F64;
+    const void *ids = nullptr, *arp = nullptr, *acol = nullptr, *aval = nullptr, *brp = nullptr, *bcol = nullptr,
+               *bval = nullptr;
+    int64_t nrows = 0, nzr = 0, nnz_a = 0, inner = 0, ncols = 0, stages = 0, b = 0;
+    int64_t pieces = 0, nnz_p = 0, nnz_c = 0, nzr_c = 0;
+};
+
 struct spg_plan_s {
     int device = 0;
     hipStream_t stream = nullptr;  // the caller's stream: every call is ordered on it
@@ -147,6 +159,11 @@ struct spg_plan_s {
 
     // distance-2 independent sets and aggregation
     DevBuf mis_key, mis_m1, mis_cand, mis_new, mis_a1, mis_flags, mis_agg1, mis_ctr;
+
+    // Sparse SUMMA stages (child plans created on first use)
+    spg_plan summa_p = nullptr, summa_s = nullptr;
+    DevBuf sm_pos, sm_piece_rp, sm_p_rp, sm_p_col, sm_p_val, sm_s_rp, sm_s_col, sm_s_val, sm_c_rp, sm_c_pos;
+    SummaState summa;
 
     // merge state
     std::vector<LayerDesc> merge_sig;
@@ -534,9 +551,12 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
                       &P->lcap, &P->lcnt, &P->slot, &P->pcol, &P->pval, &P->fb_list, &P->fb_redo, &P->sub_rp,
                       &P->sub_col, &P->sub_val, &P->sub_crp, &P->mlp_tmp, &P->sub_pos,
                       &P->mis_key, &P->mis_m1, &P->mis_cand, &P->mis_new, &P->mis_a1, &P->mis_flags, &P->mis_agg1,
-                      &P->mis_ctr})
+                      &P->mis_ctr, &P->sm_pos, &P->sm_piece_rp, &P->sm_p_rp, &P->sm_p_col, &P->sm_p_val,
+                      &P->sm_s_rp, &P->sm_s_col, &P->sm_s_val, &P->sm_c_rp, &P->sm_c_pos})
         b->release();
     if (P->sub) spg_plan_destroy(P->sub);
+    if (P->summa_p) spg_plan_destroy(P->summa_p);
+    if (P->summa_s) spg_plan_destroy(P->summa_s);
     if (P->h_stats) hipHostFree(P->h_stats);
     for (auto& r : P->prof_pending) {
         hipEventDestroy(r.beg);
@@ -1501,6 +1521,245 @@ extern "C" spg_status spgemm_merge_layers_noalloc(void* stream, spg_semiring sr,
         *out_nnz = host_buf[0];
     }
     return SPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// hypersparse row-compressed matrices and the Sparse SUMMA stages
+// ---------------------------------------------------------------------------
+static spg_status check_dcsr(const spg_dcsr* A, const char* name, spg_semiring sr, bool need_val) {
+    if (!A) return fail(SPG_ERR_ARG, std::string(name) + " is NULL");
+    if (A->nrows < 0 || A->ncols < 0 || A->nzr < 0 || A->nnz < 0)
+        return fail(SPG_ERR_ARG, std::string(name) + ": negative dimension or count");
+    if (A->nrows >= (1ll << 31) - 1 || A->ncols >= (1ll << 31) - 1)
+        return fail(SPG_ERR_INDEX_RANGE, std::string(name) + ": dimension >= 2^31");
+    if (A->nzr > A->nrows || A->nzr > A->nnz) return fail(SPG_ERR_ARG, std::string(name) + ": nzr exceeds nrows or nnz");
+    if (!A->row_ptr) return fail(SPG_ERR_ARG, std::string(name) + ".row_ptr is NULL");
+    if (A->nzr > 0 && !A->row_ids) return fail(SPG_ERR_ARG, std::string(name) + ".row_ids is NULL");
+    if (A->nnz > 0 && !A->col) return fail(SPG_ERR_ARG, std::string(name) + ".col is NULL");
+    if (need_val && A->nnz > 0 && !A->val && sr != SPG_SR_OR_AND_BOOL)
+        return fail(SPG_ERR_ARG, std::string(name) + ".val is NULL");
+    return SPG_OK;
+}
+
+// The compressed view: a CSR over the kept rows.
+static spg_csr dcsr_view(const spg_dcsr* A) {
+    return spg_csr{A->nzr, A->ncols, A->nnz, A->row_ptr, A->col, A->val};
+}
+
+static spg_status validate_dcsr(spg_plan P, const spg_dcsr* A, const char* name) {
+    const spg_csr v = dcsr_view(A);
+    SPG_TRY(validate_csr(P, &v, name));
+    if (A->nzr == 0) return SPG_OK;
+    int32_t* bad = P->small_i32.as<int32_t>() + CTR_CHECK;
+    SPG_TRY(fill_i32(P, bad, 1, 0));
+    SPG_TRY(launch(P, "validate", [&] {
+        k_validate_rows<<<grid_for(A->nzr, 256), 256, 0, cs(P)>>>(A->row_ids, A->row_ptr, A->nzr, A->nrows, bad);
+    }));
+    int32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    if (h) return fail(SPG_ERR_NOT_CANONICAL, std::string(name) + " row indices are not increasing, in range and non-empty");
+    return SPG_OK;
+}
+
+static spg_status read_i64(spg_plan P, const int64_t* dev, int64_t* out) {
+    HIP_TRY(hipMemcpyAsync(P->h_stats, dev, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    *out = P->h_stats[0];
+    return SPG_OK;
+}
+
+// pos[0..m] = exclusive count of the non-empty rows among rp's m rows.
+static spg_status nonempty_scan(spg_plan P, const int64_t* rp, int64_t m, DevBuf& buf) {
+    SPG_TRY(buf.ensure(sizeof(int64_t) * (size_t)(m + 1), "row flags"));
+    int64_t* pos = buf.as<int64_t>();
+    if (m > 0)
+        SPG_TRY(launch(P, "dcsr_flags", [&] { k_nonempty_flags<<<grid_for(m, 256), 256, 0, cs(P)>>>(rp, m, pos); }));
+    return scan_counts(P, pos, m);
+}
+
+extern "C" spg_status spg_dcsr_compress(spg_plan P, const spg_csr* A, int32_t* row_ids, int64_t* row_ptr,
+                                        int64_t* nzr) {
+    if (P) P->cur = nullptr;
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    SPG_TRY(check_csr(A, "A", SPG_SR_OR_AND_BOOL, false));
+    const bool count_pass = row_ptr == nullptr;
+    if (count_pass && !nzr) return fail(SPG_ERR_ARG, "the count call needs nzr");
+    SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
+    if (P->opts.validate && count_pass) SPG_TRY(validate_csr(P, A, "A"));
+    const int64_t m = A->nrows;
+    SPG_TRY(nonempty_scan(P, A->row_ptr, m, P->sm_c_pos));
+    const int64_t* pos = P->sm_c_pos.as<int64_t>();
+    if (count_pass) return read_i64(P, pos + m, nzr);
+    int64_t kept = 0;
+    SPG_TRY(read_i64(P, pos + m, &kept));
+    if (kept > 0 && !row_ids) return fail(SPG_ERR_ARG, "row_ids is NULL");
+    if (nzr) *nzr = kept;
+    SPG_TRY(launch(P, "dcsr_compress", [&] {
+        k_compress_rows<<<grid_for(m + 1, 256), 256, 0, cs(P)>>>(A->row_ptr, m, pos, nullptr, row_ids, row_ptr);
+    }));
+    return SPG_OK;
+}
+
+extern "C" spg_status spg_dcsr_expand(spg_plan P, const spg_dcsr* A, int64_t* row_ptr) {
+    if (P) P->cur = nullptr;
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    SPG_TRY(check_dcsr(A, "A", SPG_SR_OR_AND_BOOL, false));
+    if (!row_ptr) return fail(SPG_ERR_ARG, "row_ptr is NULL");
+    SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
+    if (P->opts.validate) SPG_TRY(validate_dcsr(P, A, "A"));
+    const int64_t m = A->nrows;
+    return launch(P, "dcsr_expand", [&] {
+        k_expand_rows<<<grid_for(m + 1, 256), 256, 0, cs(P)>>>(A->row_ids, A->row_ptr, A->nzr, m, row_ptr);
+    });
+}
+
+static spg_status summa_child(spg_plan P, spg_plan* child) {
+    if (!*child) SPG_TRY(spg_plan_create(child, (void*)P->stream, &P->opts));
+    (*child)->stream = P->stream;
+    return SPG_OK;
+}
+
+static size_t sr_val_bytes(spg_semiring sr) { return sr == SPG_SR_OR_AND_BOOL ? 1 : 8; }
+
+// The count call: piece rows, their product by B (the kept block
+// products), and the merge's symbolic pass; the fill call: the merge's
+// numeric pass into the caller's arrays and the compaction of the rows.
+extern "C" spg_status spgemm_summa_local(spg_plan P, spg_semiring sr, const spg_dcsr* A, const spg_csr* B,
+                                         int64_t stages, int64_t b, int32_t* c_row_ids, int64_t* c_row_ptr,
+                                         int32_t* c_col, void* c_val, int64_t* c_nzr, int64_t* c_nnz,
+                                         int64_t* stage_nnz) {
+    if (P) P->cur = nullptr;
+    if (!P) return fail(SPG_ERR_ARG, "plan is NULL");
+    if ((int)sr < 0 || (int)sr > 2) return fail(SPG_ERR_ARG, "unknown semiring");
+    const bool count_pass = c_row_ptr == nullptr;
+    SPG_TRY(check_dcsr(A, "A", sr, true));
+    SPG_TRY(check_csr(B, "B", sr, true));
+    if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
+    if (stages < 1 || b < 1) return fail(SPG_ERR_ARG, "stages and b must be positive");
+    if (A->ncols % stages) return fail(SPG_ERR_ARG, "the stage count must divide the inner dimension");
+    if ((A->ncols / stages) % b) return fail(SPG_ERR_ARG, "b must divide the inner width of a stage");
+    if (b > INT32_MAX) b = INT32_MAX;  // one block: every column index is below 2^31
+    SummaState& S = P->summa;
+    const spg_csr Av = dcsr_view(A);
+    if (count_pass) {
+        if (!c_nzr || !c_nnz) return fail(SPG_ERR_ARG, "the count call needs c_nzr and c_nnz");
+        S = SummaState();
+        S.sr = sr;
+        S.ids = A->row_ids; S.arp = A->row_ptr; S.acol = A->col; S.aval = A->val;
+        S.brp = B->row_ptr; S.bcol = B->col; S.bval = B->val;
+        S.nrows = A->nrows; S.nzr = A->nzr; S.nnz_a = A->nnz; S.inner = A->ncols; S.ncols = B->ncols;
+        S.stages = stages; S.b = b;
+        SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
+        if (P->opts.validate) {
+            SPG_TRY(validate_dcsr(P, A, "A"));
+            SPG_TRY(validate_csr(P, B, "B"));
+        }
+        const int64_t nzr = A->nzr;
+        if (nzr == 0 || A->nnz == 0 || A->ncols == 0) {
+            S.mode = 0;
+        } else {
+            SPG_TRY(P->sm_c_rp.ensure(sizeof(int64_t) * (size_t)(nzr + 1), "stage result rows"));
+            int64_t* crp = P->sm_c_rp.as<int64_t>();
+            int64_t nnz_c = 0;
+            if (A->ncols / b <= 1) {
+                // one block: the stage product is the result
+                S.mode = 1;
+                SPG_TRY(summa_child(P, &P->summa_p));
+                SPG_TRY(spgemm_symbolic(P->summa_p, sr, &Av, B, 0, A->ncols, crp, &nnz_c));
+                S.nnz_p = nnz_c;
+            } else {
+                S.mode = 2;
+                const int64_t nnz = A->nnz;
+                // cut the rows into pieces at the block boundaries
+                SPG_TRY(P->sm_pos.ensure(sizeof(int64_t) * (size_t)(nnz + 1), "piece flags"));
+                int64_t* pos = P->sm_pos.as<int64_t>();
+                SPG_TRY(launch(P, "summa_pieces", [&] {
+                    k_piece_flags<<<grid_for(nnz, 256), 256, 0, cs(P)>>>(A->col, nnz, (uint32_t)b, pos);
+                }));
+                SPG_TRY(launch(P, "summa_pieces", [&] {
+                    k_piece_row_starts<<<grid_for(nzr, 256), 256, 0, cs(P)>>>(A->row_ptr, nzr, pos);
+                }));
+                SPG_TRY(scan_counts(P, pos, nnz));
+                int64_t G = 0;
+                SPG_TRY(read_i64(P, pos + nnz, &G));
+                if (G > MAX_ROWS_PER_CALL)
+                    return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 row pieces in one call; split A by rows");
+                S.pieces = G;
+                SPG_TRY(P->sm_piece_rp.ensure(sizeof(int64_t) * (size_t)(G + 1), "piece rows"));
+                int64_t* prp = P->sm_piece_rp.as<int64_t>();
+                SPG_TRY(launch(P, "summa_pieces", [&] {
+                    k_piece_rows<<<grid_for(nnz + 1, 256), 256, 0, cs(P)>>>(pos, nnz, prp);
+                }));
+                // the kept block products: piece rows times B
+                const spg_csr Ap{G, A->ncols, nnz, prp, A->col, A->val};
+                SPG_TRY(summa_child(P, &P->summa_p));
+                SPG_TRY(P->sm_p_rp.ensure(sizeof(int64_t) * (size_t)(G + 1), "stage products"));
+                int64_t nnz_p = 0;
+                SPG_TRY(spgemm_symbolic(P->summa_p, sr, &Ap, B, 0, A->ncols, P->sm_p_rp.as<int64_t>(), &nnz_p));
+                S.nnz_p = nnz_p;
+                SPG_TRY(P->sm_p_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz_p, 1), "stage products"));
+                SPG_TRY(P->sm_p_val.ensure(sr_val_bytes(sr) * (size_t)std::max<int64_t>(nnz_p, 1), "stage products"));
+                SPG_TRY(spgemm_numeric(P->summa_p, sr, &Ap, B, 0, A->ncols, P->sm_p_rp.as<int64_t>(),
+                                       P->sm_p_col.as<int32_t>(), P->sm_p_val.p));
+                // the selection matrix of the merge
+                SPG_TRY(P->sm_s_rp.ensure(sizeof(int64_t) * (size_t)(nzr + 1), "merge selection"));
+                SPG_TRY(P->sm_s_col.ensure(sizeof(int32_t) * (size_t)G, "merge selection"));
+                SPG_TRY(P->sm_s_val.ensure(sr_val_bytes(sr) * (size_t)G, "merge selection"));
+                const int64_t nt = std::max<int64_t>(nzr + 1, G);
+                int64_t* srp = P->sm_s_rp.as<int64_t>();
+                int32_t* scol = P->sm_s_col.as<int32_t>();
+                void* sval = P->sm_s_val.p;
+                SPG_TRY(launch(P, "summa_selection", [&] {
+                    if (sr == SPG_SR_PLUS_TIMES_F64)
+                        k_selection<SR_F64><<<grid_for(nt, 256), 256, 0, cs(P)>>>(A->row_ptr, nzr, pos, G, srp, scol, sval);
+                    else if (sr == SPG_SR_PLUS_TIMES_I64)
+                        k_selection<SR_I64><<<grid_for(nt, 256), 256, 0, cs(P)>>>(A->row_ptr, nzr, pos, G, srp, scol, sval);
+                    else
+                        k_selection<SR_BOOL><<<grid_for(nt, 256), 256, 0, cs(P)>>>(A->row_ptr, nzr, pos, G, srp, scol, sval);
+                }));
+                const spg_csr Sm{nzr, G, G, srp, scol, sval};
+                const spg_csr Pm{G, B->ncols, nnz_p, P->sm_p_rp.as<int64_t>(), P->sm_p_col.as<int32_t>(), P->sm_p_val.p};
+                SPG_TRY(summa_child(P, &P->summa_s));
+                SPG_TRY(spgemm_symbolic(P->summa_s, sr, &Sm, &Pm, 0, G, crp, &nnz_c));
+            }
+            S.nnz_c = nnz_c;
+            // rows of the result that came out empty are dropped
+            SPG_TRY(nonempty_scan(P, crp, nzr, P->sm_c_pos));
+            SPG_TRY(read_i64(P, P->sm_c_pos.as<int64_t>() + nzr, &S.nzr_c));
+        }
+        S.valid = true;
+        *c_nzr = S.nzr_c;
+        *c_nnz = S.nnz_c;
+        if (stage_nnz) *stage_nnz = S.nnz_p;
+        return SPG_OK;
+    }
+    // fill call: same operands as the count call
+    if (!S.valid || S.sr != sr || S.ids != A->row_ids || S.arp != A->row_ptr || S.acol != A->col ||
+        S.aval != A->val || S.brp != B->row_ptr || S.bcol != B->col || S.bval != B->val || S.nrows != A->nrows ||
+        S.nzr != A->nzr || S.nnz_a != A->nnz || S.inner != A->ncols || S.ncols != B->ncols || S.stages != stages ||
+        S.b != b)
+        return fail(SPG_ERR_STATE, "the stage fill call needs the matching count call first");
+    if (S.nzr_c > 0 && !c_row_ids) return fail(SPG_ERR_ARG, "c_row_ids is NULL");
+    if (S.nnz_c > 0 && !c_col) return fail(SPG_ERR_ARG, "c_col is NULL");
+    if (S.mode == 0) return fill_i64(P, c_row_ptr, 1, 0);
+    const int64_t* crp = P->sm_c_rp.as<int64_t>();
+    if (S.mode == 1) {
+        SPG_TRY(summa_child(P, &P->summa_p));
+        SPG_TRY(spgemm_numeric(P->summa_p, sr, &Av, B, 0, A->ncols, crp, c_col, c_val));
+    } else {
+        const int64_t G = S.pieces;
+        const spg_csr Sm{A->nzr, G, G, P->sm_s_rp.as<int64_t>(), P->sm_s_col.as<int32_t>(), P->sm_s_val.p};
+        const spg_csr Pm{G, B->ncols, S.nnz_p, P->sm_p_rp.as<int64_t>(), P->sm_p_col.as<int32_t>(), P->sm_p_val.p};
+        SPG_TRY(summa_child(P, &P->summa_s));
+        SPG_TRY(spgemm_numeric(P->summa_s, sr, &Sm, &Pm, 0, G, crp, c_col, c_val));
+    }
+    P->cur = nullptr;
+    const int64_t nzr = A->nzr;
+    const int64_t* cpos = P->sm_c_pos.as<int64_t>();
+    return launch(P, "dcsr_compress", [&] {
+        k_compress_rows<<<grid_for(nzr + 1, 256), 256, 0, cs(P)>>>(crp, nzr, cpos, A->row_ids, c_row_ids, c_row_ptr);
+    });
 }
 
 // ---------------------------------------------------------------------------

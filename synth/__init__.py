@@ -19,6 +19,8 @@ from .gen import (  # noqa: F401
     random_csr,
     with_values,
     layer_bounds,
+    submatrix,
+    process_share,
     galerkin_batch,
     G500,
     SSCA,

@@ -285,3 +285,30 @@ def layer_bounds(K: int, c: int):
     """Contiguous inner-dimension layers K_l = [floor(l*K/c), floor((l+1)*K/c)),
     the split distribution of Section 4 along the third grid dimension."""
     return [((l * K) // c, ((l + 1) * K) // c) for l in range(c)]
+
+
+def submatrix(M: CSR, r0: int, r1: int, c0: int, c1: int) -> CSR:
+    """Rows [r0, r1) and columns [c0, c1) of M, renumbered from 0."""
+    rp = M.row_ptr
+    s, e = int(rp[r0]), int(rp[r1])
+    rows = np.repeat(np.arange(r1 - r0, dtype=np.int64), np.diff(rp[r0:r1 + 1]))
+    cols = M.col[s:e].astype(np.int64)
+    keep = (cols >= c0) & (cols < c1)
+    val = None if M.val is None else M.val[s:e][keep]
+    out = canonical_from_coo(r1 - r0, c1 - c0, rows[keep], cols[keep] - c0, val, dup="first")
+    return out
+
+
+def process_share(M: CSR, grid: int, layers: int, i: int, j: int, k: int):
+    """The blocks of A = B = M that process P(i, j, k) of a grid x grid x
+    layers process grid multiplies in its Sparse SUMMA stages: A's rows of
+    process row i and B's columns of process column j, both over the inner
+    range of layer k (the layer's n/layers inner indices, which the grid
+    stages cover in `grid` equal stage blocks).  Returns (A_loc, B_loc)."""
+    n = M.nrows
+    if n % grid or n % layers or (n // layers) % grid:
+        raise ValueError("the grid must divide the dimension")
+    mb, kb = n // grid, n // layers
+    A = submatrix(M, i * mb, (i + 1) * mb, k * kb, (k + 1) * kb)
+    B = submatrix(M, k * kb, (k + 1) * kb, j * mb, (j + 1) * mb)
+    return A, B
