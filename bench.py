@@ -48,10 +48,125 @@ def parse():
                     help="skip the second pass that times every kernel alone (roofline_isolated)")
     ap.add_argument("--tune-cache", default=None, help="JSON-lines cache of the batched autotuner")
     ap.add_argument("--tune-budget-ms", type=int, default=3000)
-    ap.add_argument("--mode", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2: the headline product (default); c3, c4, c5: only that secondary "
+    ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="CSV",
+                    help="only print a markdown table of per-kernel averages of rocprofv3 --pmc csv files")
+    ap.add_argument("--trace-summary", default=None, metavar="CSV",
+                    help="only print a markdown table of a rocprofv3 kernel_stats.csv")
+    ap.add_argument("--traffic-summary", nargs=5, default=None,
+                    metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="only write profiles/pmc_traffic_<WORKLOAD>.json from FETCH_SIZE / WRITE_SIZE passes "
+                         "and print its table")
+    ap.add_argument("--traffic-commands", default="", help="the counter commands, recorded in the json")
+    ap.add_argument("--mode", default="c2", choices=["c2", "c3", "c4", "c5", "summa"],
+                    help="c2: the headline product (default); c3, c4, c5, summa: only that secondary "
                          "workload, with its per-kernel times (for profiling)")
     return ap.parse_args()
+
+
+def _kernel_short(name: str) -> str:
+    name = name.split("(")[0].strip()
+    return name[5:] if name.startswith("void ") else name
+
+
+def pmc_summary(paths, top=30):
+    """Per-kernel averages over the dispatches of rocprofv3 --pmc csv files:
+    duration, and each counter per dispatch; SQ_INSTS_* also per wave."""
+    import csv
+    from collections import defaultdict
+    recs = defaultdict(lambda: {"disp": {}, "c": defaultdict(list)})
+    counters = []
+    for p in paths:
+        with open(p) as f:
+            for r in csv.DictReader(f):
+                k = _kernel_short(r["Kernel_Name"])
+                d = recs[k]
+                did = (p, r["Dispatch_Id"])
+                d["disp"][did] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                d["c"][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                if r["Counter_Name"] not in counters:
+                    counters.append(r["Counter_Name"])
+    rows = []
+    for k, d in recs.items():
+        n = len(d["disp"])
+        dur = sum(d["disp"].values()) / n / 1e3
+        avg = {c: sum(v) / len(v) for c, v in d["c"].items()}
+        rows.append((dur * n, k, n, dur, avg))
+    rows.sort(key=lambda x: -x[0])
+    cols = list(counters)
+    per_wave = [c for c in cols if c.startswith("SQ_INSTS_")] if "SQ_WAVES" in cols else []
+    head = ["kernel", "dispatches", "avg us"] + cols + [c + "/wave" for c in per_wave]
+    print("| " + " | ".join(head) + " |")
+    print("|" + "---|" + "---:|" * (len(head) - 1))
+    for _, k, n, dur, avg in rows[:top]:
+        vals = ["`%s`" % k, str(n), "%.1f" % dur]
+        for c in cols:
+            v = avg.get(c)
+            vals.append("" if v is None else ("%.3g" % v if abs(v) < 1000 else "%.0f" % v))
+        for c in per_wave:
+            w = avg.get("SQ_WAVES") or 0
+            vals.append("%.1f" % (avg.get(c, 0.0) / w) if w else "")
+        print("| " + " | ".join(vals) + " |")
+
+
+def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, commands):
+    """Per-kernel HBM bytes per launch from one FETCH_SIZE and one WRITE_SIZE
+    pass (KiB per dispatch), each scaled by what the same counter reads for
+    the 256 MiB device copy of --copy-calibration; writes
+    profiles/pmc_traffic_<workload>.json (stamped with the SHA-256 of the
+    kernel sources) and prints the markdown table."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path):
+        acc = defaultdict(list)
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                acc[_kernel_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return acc
+
+    def copy_kib(path):
+        v = per_kernel(path).get("__amd_rocclr_copyBuffer")
+        if not v:
+            raise SystemExit("no device copy in %s" % path)
+        return sum(v) / len(v)
+
+    copy_kib_total = (256 << 20) / 1024.0
+    ff = copy_kib_total / copy_kib(copy_fetch_csv)
+    wf = copy_kib_total / copy_kib(copy_write_csv)
+    fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+    kernels = {}
+    for k in fe:
+        if k not in wr:
+            continue
+        kernels[k] = {"launches": len(fe[k]),
+                      "fetch_bytes_per_launch": int(sum(fe[k]) / len(fe[k]) * 1024 * ff),
+                      "write_bytes_per_launch": int(sum(wr[k]) / len(wr[k]) * 1024 * wf)}
+    d = {"workload": workload, "source_sha256": kernel_source_sha256(), "fetch_factor": round(ff, 4),
+         "write_factor": round(wf, 4), "commands": commands, "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic_%s.json" % workload), "w") as f:
+        json.dump(d, f, indent=1)
+    print("| kernel | launches | fetch MB/launch | write MB/launch |")
+    print("|---|---:|---:|---:|")
+    for k, v in sorted(kernels.items(), key=lambda kv: -(kv[1]["fetch_bytes_per_launch"] +
+                                                          kv[1]["write_bytes_per_launch"]))[:20]:
+        print("| `%s` | %d | %.1f | %.1f |" % (k, v["launches"], v["fetch_bytes_per_launch"] / 1e6,
+                                              v["write_bytes_per_launch"] / 1e6))
+    print()
+    print("Copy calibration: FETCH_SIZE factor %.4f, WRITE_SIZE factor %.4f; kernel sources SHA-256 `%s`"
+          % (ff, wf, d["source_sha256"]))
+
+
+def trace_summary(path, top=25):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    print("| kernel | calls | total us | average us | % |")
+    print("|---|---:|---:|---:|---:|")
+    for r in rows[:top]:
+        print("| `%s` | %s | %.1f | %.1f | %.2f |" % (_kernel_short(r["Name"]), r["Calls"],
+                                                    float(r["TotalDurationNs"]) / 1e3,
+                                                    float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
 
 
 def copy_calibration():
@@ -122,9 +237,10 @@ def kernel_source_sha256() -> str:
 
 
 def measured_traffic(kernel: str, workload: str = "c2"):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    kernels changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` (a launch name such as num_rankc)
+    from the committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated, written by --traffic-summary), or None when the sources
+    changed since the counters were taken or the name is ambiguous."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -132,9 +248,11 @@ def measured_traffic(kernel: str, workload: str = "c2"):
         d = json.load(f)
     if d.get("source_sha256") != kernel_source_sha256():
         return None
-    k = d["kernels"].get(kernel)
-    if k is None:
+    prefix = "spg::k_%s<" % kernel
+    hits = [v for k, v in d["kernels"].items() if k.startswith(prefix)]
+    if len(hits) != 1:
         return None
+    k = hits[0]
     return {"fetch_bytes": k["fetch_bytes_per_launch"], "write_bytes": k["write_bytes_per_launch"],
             "total_bytes": k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"],
             "source": "profiles/pmc_traffic_%s.md" % workload}
@@ -378,6 +496,63 @@ def heap_modes(reps=5):
     return out
 
 
+def summa_modes(reps=5):
+    """One process's Sparse SUMMA stages (Algorithm 2 stage loop, blocking b)
+    on hypersparse blocks: the share of process P(0,1,1) of a 16 x 16 x 4
+    grid squaring R-MAT G500 scale 20 (65,536 rows, 262,144 inner indices in
+    16 stages, 65,536 columns), A as DCSR.  Times the count + fill calls for
+    several b, the direct product of the DCSR rows (one block) and the same
+    product on the uncompressed CSR rows.
+
+    Byte model of the staged call (w = value bytes, G = row pieces):
+    W = nnzA (4 + w + 16) + 4 flops (symbolic gathers) + flops (4 + w)
+        + 2 nnzP (4 + w) + nnzC (4 + w) + 16 (G + nzr)
+    (A read with its B row extents, B gathered twice, the block products
+    written and read back by the merge, C written, piece and row extents)."""
+    import numpy as np
+    import torch
+
+    import paper_1510_00844_amd as spg
+    import synth
+    M = synth.rmat(20, 16, synth.G500, seed=3)
+    A, B = synth.process_share(M, 16, 4, 0, 1, 1)
+    del M
+    dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
+    dB = spg.DeviceCSR.from_arrays(B.nrows, B.ncols, B.row_ptr, B.col, B.val)
+    plan = spg.Plan()
+    D = spg.dcsr_compress(plan, dA)
+    t_csr, C = _time(lambda: spg.spgemm(plan, "f64", dA, dB), reps)
+    flops = plan.stats()["flops"]
+    nnz_c = C.nnz
+    del C
+    w = 8
+    nz = np.diff(A.row_ptr) > 0
+    out = {"workload": "Sparse SUMMA share of P(0,1,1), 16x16x4 grid, R-MAT G500 scale 20 squared: "
+                       "A_loc 65536 x 262144 (DCSR), B_loc 262144 x 65536, 16 stages, FP64",
+           "nnz_a": A.nnz, "nzr_a": int(nz.sum()), "nnz_b": B.nnz, "flops": flops, "nnz_c": nnz_c,
+           "csr_product_ms": round(t_csr, 4)}
+    t_dir, (Cd, _) = _time(lambda: spg.spgemm_summa_local(plan, "f64", D, dB, 1, A.ncols), reps)
+    out["dcsr_product_ms"] = round(t_dir, 4)
+    assert Cd.nnz == nnz_c
+    del Cd
+    for b in (16384, 4096, 1024):
+        t, (Cs, snnz) = _time(lambda: spg.spgemm_summa_local(plan, "f64", D, dB, 16, b), reps)
+        assert Cs.nnz == nnz_c
+        cols = A.col.astype(np.int64) // b
+        rows = np.repeat(np.arange(A.nrows), np.diff(A.row_ptr))
+        pieces = int(np.count_nonzero(np.diff(rows * (A.ncols // b + 1) + cols, prepend=-1)))
+        W = A.nnz * (4 + w + 16) + 4.0 * flops + flops * (4 + w) + 2.0 * snnz * (4 + w) + nnz_c * (4 + w) \
+            + 16.0 * (pieces + int(nz.sum()))
+        out["b%d" % b] = {"blocks": A.ncols // b, "pieces": pieces, "stage_nnz": snnz,
+                          "stage_nnz_over_nnz_c": round(snnz / max(nnz_c, 1), 3), "ms": round(t, 4),
+                          "gflops": round(2.0 * flops / t / 1e6, 3), "model_bytes": int(W),
+                          "hbm_model_gbs": round(W / t / 1e6, 2), "hbm_model_frac": round(W / t / 1e6 / HBM_PEAK_GBS, 4)}
+        del Cs
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def kernel_table(plan, steps):
     out = {}
     for name, (launches, total) in plan.profile_read().items():
@@ -398,7 +573,10 @@ def secondary_mode(args):
         out.update(batched_modes(args, reps=args.steps))
     elif args.mode == "c3":
         out.update(layered_modes(args, profile=True))
-        out["heap_vs_hash"] = heap_modes()
+        if not args.no_extras:
+            out["heap_vs_hash"] = heap_modes()
+    elif args.mode == "summa":
+        out.update(summa_modes(reps=args.steps))
     else:
         A = synth.rmat(19, 16, synth.G500, seed=6)
         dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
@@ -420,16 +598,25 @@ def secondary_mode(args):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.traffic_commands)
+        return
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(run with --gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
         return
     if args.mode != "c2":
         secondary_mode(args)
         return
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
-              "(run with --gpus 1)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
     import numpy as np
     import torch
 
@@ -598,6 +785,7 @@ def main():
         extras.update(learned_modes(A, dA, args))
         extras["c4_batched"] = batched_modes(args)
         extras["c3_layers"] = layered_modes(args)
+        extras["summa_s20_share"] = summa_modes()
         out["modes"] = extras
     if not args.no_cpu_baseline:
         import oracle
