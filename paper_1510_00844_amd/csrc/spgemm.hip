@@ -963,12 +963,13 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
     const int nstreams = std::max(1, std::min(P->opts.streams, NAUX + 1));
     SPG_TRY(fork_streams(P));
     // the numeric pass's split table (B and W only) on the last helper stream
-    // rank-chunk items are possible (chunk counts recorded); the split table
-    // is needed when a row has more than one chunk
+    // when rank-chunk items are possible (chunk counts recorded, bitmap rows
+    // expected) and a row has more than one chunk; the numeric pass builds
+    // it for the column-chunked rows otherwise
     const bool chunked = bp.dense_ok && bp.chunk_counts;
     P->split_ready = false;
     P->bm_cap = 0;
-    if (chunked && b.ncols > W) {
+    if (chunked && b.ncols > W && bitmap_rows > 0) {
         P->cur = nstreams > 1 ? P->aux[nstreams - 2] : P->stream;
         SPG_TRY(build_split_table(P, b, W));
         P->split_ready = true;
