@@ -132,7 +132,10 @@ spg_status spg_plan_create(spg_plan* plan, void* stream, const spg_opts* opts);
 spg_status spg_plan_destroy(spg_plan plan);
 spg_status spg_plan_set_stream(spg_plan plan, void* stream);
 
-/* Symbolic phase: per-row output counts of C = A(:,K) B(K,:), K = [k_lo,k_hi).
+/* Symbolic phase of the row-wise product (Section 3, Algorithm 1 written by
+ * rows; Section 4.4 for the layer window): row i of C = A(:,K) B(K,:),
+ * K = [k_lo,k_hi), stores the union of the column sets of the rows B(k,:)
+ * with A(i,k) stored and k in K; this call counts each row's union.
  * c_row_ptr: device, m+1 entries, caller-owned; receives the exclusive
  * prefix sum of the row counts (c_row_ptr[m] = nnz(C)).
  * c_nnz: host; if not NULL it receives nnz(C) and the stream is synchronized.
@@ -141,7 +144,9 @@ spg_status spg_plan_set_stream(spg_plan plan, void* stream);
 spg_status spgemm_symbolic(spg_plan plan, spg_semiring sr, const spg_csr* A, const spg_csr* B,
                            int64_t k_lo, int64_t k_hi, int64_t* c_row_ptr, int64_t* c_nnz);
 
-/* Numeric phase: fills c_col (int32) and c_val (typed as the semiring) for the
+/* Numeric phase (Section 3, Algorithm 1 by rows: C(i,:) is the semiring sum
+ * over k in the window of A(i,k) times B(k,:)): fills c_col (int32) and
+ * c_val (typed as the semiring) for the
  * row pointers computed by the last spgemm_symbolic on this plan, which must
  * have had the same A, B and window (SPG_ERR_STATE otherwise).  Rows come out
  * sorted by column.  c_val may be NULL to produce the structure only. */
@@ -343,7 +348,10 @@ spg_status spgemm_learned_fetch(spg_plan plan, const spg_csr* A, const spg_csr* 
  * sequence into one HIP graph, which later calls with the same descriptors
  * (same pointers and sizes) replay without any host synchronization.  Values
  * may change between such calls; the row pointers and column indices behind
- * the descriptors must not (the graph reuses the sizes of the first call).
+ * the descriptors must not: later calls (graph or not) run only the value
+ * work (assembly, the two numeric passes, the split into instances) with
+ * the sizes, bin lists and saved row bitmaps of the first call, whose
+ * symbolic passes are not repeated.
  * out[b] points into plan-owned memory (column indices local to the
  * instance), valid until the next call with other descriptors or
  * spg_plan_destroy.  Calls that overlap on one plan race.

@@ -598,6 +598,15 @@ static spg_status check_csr(const spg_csr* M, const char* name, spg_semiring sr,
 // grid to 2^32 threads in x, so one call takes at most 2^22 rows.
 static const int64_t MAX_ROWS_PER_CALL = 1ll << 22;
 
+// The product kernels add the lengths of up to 1024 B rows of one A row in
+// int32.  Those rows are distinct, so the sum is at most nnz(B), and each
+// is at most ncols(B) long: it fits when either bound is below 2^31.
+static spg_status check_batch_sums(const spg_csr* B) {
+    if (B->nnz >= (1ll << 31) - 1 && B->ncols * 1024 >= (1ll << 31) - 1)
+        return fail(SPG_ERR_INDEX_RANGE, "B holds 2^31 or more entries and more than 2^21 columns; split B by columns");
+    return SPG_OK;
+}
+
 static Csr view(const spg_csr* M) { return Csr{M->nrows, M->ncols, M->nnz, M->row_ptr, M->col, M->val}; }
 
 // validation: row_ptr[0]==0, nondecreasing, row_ptr[m]==nnz, columns in range and increasing
@@ -888,6 +897,7 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
     SPG_TRY(check_csr(B, "B", sr, false));
     if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
     if (A->nrows > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split A by rows");
+    SPG_TRY(check_batch_sums(B));
     if (k_lo < 0 || k_hi < k_lo || k_hi > A->ncols) return fail(SPG_ERR_ARG, "window must satisfy 0 <= k_lo <= k_hi <= A.ncols");
     if (!c_row_ptr) return fail(SPG_ERR_ARG, "c_row_ptr is NULL");
     P->have_symbolic = false;
@@ -2003,6 +2013,7 @@ extern "C" spg_status spgemm_learned_run(spg_plan P, spg_semiring sr, const spg_
     SPG_TRY(check_csr(B, "B", sr, true));
     if (A->ncols != B->nrows) return fail(SPG_ERR_SHAPE, "A.ncols != B.nrows");
     if (A->nrows > MAX_ROWS_PER_CALL) return fail(SPG_ERR_INDEX_RANGE, "more than 2^22 rows in one call; split A by rows");
+    SPG_TRY(check_batch_sums(B));
     if (k_lo < 0 || k_hi < k_lo || k_hi > A->ncols) return fail(SPG_ERR_ARG, "window must satisfy 0 <= k_lo <= k_hi <= A.ncols");
     if (!c_nnz) return fail(SPG_ERR_ARG, "c_nnz is NULL");
     if (!(margin >= 0.f) || margin > 100.f) return fail(SPG_ERR_ARG, "margin must be in [0, 100]");
@@ -2256,18 +2267,22 @@ static spg_status galerkin_sequence(spg_plan P, GalerkinState* G, bool eager) {
     spg_csr R{G->rows_r, G->cols_r, G->nnz_r, G->r_rp.as<int64_t>(), G->r_col.as<int32_t>(), G->r_val.p};
     const size_t w = vw;
     int64_t nt = G->nnz_t, nc = G->nnz_c;
-    if (eager) SPG_TRY(G->t_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched T"));
-    SPG_TRY(spgemm_symbolic(G->p1, G->sr, &RT, &A, 0, A.nrows, G->t_rp.as<int64_t>(), eager ? &nt : nullptr));
+    // The symbolic passes run in the eager call only: the structure is fixed
+    // between replays, so its row pointers, bin lists, saved bitmaps and
+    // work items (kept by the two product plans, which nothing else uses)
+    // serve every replay's numeric passes.
     if (eager) {
+        SPG_TRY(G->t_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched T"));
+        SPG_TRY(spgemm_symbolic(G->p1, G->sr, &RT, &A, 0, A.nrows, G->t_rp.as<int64_t>(), &nt));
         G->nnz_t = nt;
         SPG_TRY(G->t_col.ensure(4 * (size_t)std::max<int64_t>(nt, 1), "batched T"));
         SPG_TRY(G->t_val.ensure(w * (size_t)std::max<int64_t>(nt, 1), "batched T"));
     }
     SPG_TRY(spgemm_numeric(G->p1, G->sr, &RT, &A, 0, A.nrows, G->t_rp.as<int64_t>(), G->t_col.as<int32_t>(), G->t_val.p));
     spg_csr T{G->rows_rt, G->rows_r, G->nnz_t, G->t_rp.as<int64_t>(), G->t_col.as<int32_t>(), G->t_val.p};
-    if (eager) SPG_TRY(G->c_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched C"));
-    SPG_TRY(spgemm_symbolic(G->p2, G->sr, &T, &R, 0, R.nrows, G->c_rp.as<int64_t>(), eager ? &nc : nullptr));
     if (eager) {
+        SPG_TRY(G->c_rp.ensure(8 * (size_t)(G->rows_rt + 1), "batched C"));
+        SPG_TRY(spgemm_symbolic(G->p2, G->sr, &T, &R, 0, R.nrows, G->c_rp.as<int64_t>(), &nc));
         G->nnz_c = nc;
         SPG_TRY(G->c_col.ensure(4 * (size_t)std::max<int64_t>(nc, 1), "batched C"));
         SPG_TRY(G->c_val.ensure(w * (size_t)std::max<int64_t>(nc, 1), "batched C"));

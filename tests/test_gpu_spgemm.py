@@ -322,6 +322,25 @@ def test_errors(plan):
         spg.spgemm_symbolic(vplan, "f64", bad, to_dev(synth.random_csr(4, 2, 0.5, 3)))
     assert e.value.name == "SPG_ERR_NOT_CANONICAL"
     vplan.close()
+    # a B whose row-length sums could exceed int32 inside the product
+    # kernels (2^31 entries over more than 2^21 columns) is refused before
+    # any launch; the descriptor's arrays are small stand-ins, never read
+    rows = 1 << 22
+    huge = spg.DeviceCSR(rows, 1 << 22, torch.zeros(2, dtype=torch.int64, device=plan.device),
+                         torch.zeros(1, dtype=torch.int32, device=plan.device),
+                         torch.zeros(1, dtype=torch.float64, device=plan.device))
+    a = spg.DeviceCSR(4, rows, torch.zeros(5, dtype=torch.int64, device=plan.device),
+                      torch.zeros(1, dtype=torch.int32, device=plan.device),
+                      torch.zeros(1, dtype=torch.float64, device=plan.device))
+    import ctypes
+    hb, ha = huge._c("f64"), a._c("f64")
+    hb.nnz = 1 << 31
+    hb.nrows = rows
+    rp = torch.zeros(5, dtype=torch.int64, device=plan.device)
+    nnz = ctypes.c_int64()
+    st = spg.lib().spgemm_symbolic(plan.handle, 0, ctypes.byref(ha), ctypes.byref(hb), 0, rows,
+                                   ctypes.c_void_p(rp.data_ptr()), ctypes.byref(nnz))
+    assert st == 4  # SPG_ERR_INDEX_RANGE
 
 
 @pytest.mark.parametrize("opts", [
