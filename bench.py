@@ -315,6 +315,8 @@ def learned_modes(A2, dA2, args):
         g = lambda t: round(2.0 * flops / (t * 1e-3) / 1e9, 3)
         res[name + "_plain"] = {"ms": round(t_plain, 4), "gflops": g(t_plain), "flops": flops, "nnz_c": nnz}
         res[name + "_learned"] = {"ms": round(t_l, 4), "gflops": g(t_l), "speedup_vs_plain": round(t_plain / t_l, 3),
+                                  "single_pass_share_of_c": round(st_l["nnz_single"] / max(nnz, 1), 4),
+                                  "flops_per_output": round(flops / max(nnz, 1), 3),
                                   "stats": {k: v for k, v in st_l.items() if k != "bin_rows"}}
         res[name + "_upper_bound_sizing"] = {"ms": round(t_u, 4), "gflops": g(t_u),
                                              "stats": {k: v for k, v in st_u.items() if k != "bin_rows"}}
