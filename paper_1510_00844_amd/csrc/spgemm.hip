@@ -113,6 +113,7 @@ struct spg_plan_s {
     hipStream_t cur = nullptr;     // stream the next launch goes to
     hipStream_t aux[NAUX] = {};
     hipEvent_t ev_fork = nullptr, ev_join[NAUX] = {};
+    hipEvent_t ev_host = nullptr;  // the host waits for read-backs on it
     spg_opts opts;
     int max_lds = 65536;
     int num_cu = 256;
@@ -122,7 +123,7 @@ struct spg_plan_s {
     DevBuf merge_len, mbin, mlists, mstats, mctr, bm_save, heavy_idx, chunk_save, rank_items;
     DevBuf lpt_hist, lpt_tmp;  // ordering of heavy bins by work
     const int64_t* out_pos = nullptr;  // numeric output offsets per row (set while a sub-product writes into a full one)
-    int64_t* h_stats = nullptr;  // pinned, 4*NBINS + 8
+    int64_t* h_stats = nullptr;  // pinned, STATS_WORDS + 8 (nnz of the last read-back at STATS_WORDS)
 
     Signature sig;
     int64_t sig_rows = 0;       // rows of the current symbolic call (bounds launch grids)
@@ -517,12 +518,13 @@ extern "C" spg_status spg_plan_create(spg_plan* out, void* stream, const spg_opt
             return fail(SPG_ERR_HIP, "helper stream creation failed");
         }
     }
-    if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_host, hipEventDisableTiming) != hipSuccess) {
         hipGetLastError();
         delete P;
         return fail(SPG_ERR_HIP, "event creation failed");
     }
-    if (hipHostMalloc((void**)&P->h_stats, sizeof(int64_t) * STATS_WORDS, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&P->h_stats, sizeof(int64_t) * (STATS_WORDS + 8), hipHostMallocDefault) != hipSuccess) {
         delete P;
         hipGetLastError();
         return fail(SPG_ERR_OOM, "pinned host allocation failed");
@@ -568,6 +570,7 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
         if (P->ev_join[k]) hipEventDestroy(P->ev_join[k]);
     }
     if (P->ev_fork) hipEventDestroy(P->ev_fork);
+    if (P->ev_host) hipEventDestroy(P->ev_host);
     delete P;
     return SPG_OK;
 }
@@ -840,15 +843,28 @@ static spg_status build_split_table(spg_plan P, Csr b, int32_t W) {
     return SPG_OK;
 }
 
+// Waits on the host for the work queued so far on the plan's stream by
+// polling an event: the read-backs on the product's path are short, and a
+// poll wakes sooner than a blocking wait.
+static spg_status host_wait(spg_plan P) {
+    HIP_TRY(hipEventRecord(P->ev_host, P->stream));
+    hipError_t e;
+    while ((e = hipEventQuery(P->ev_host)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) return fail(SPG_ERR_HIP, std::string("read-back: ") + hipGetErrorString(e));
+    return SPG_OK;
+}
+
 // Reads back (synchronizing) the classification counts of the last
 // symbolic call and nnz(C); the bitmap bin's count sizes the saved bitmaps
 // of the next call with the same operands.
 static spg_status read_counts(spg_plan P, const int64_t* c_row_ptr, int64_t m) {
     const int64_t* stats = P->stats.as<int64_t>();
     HIP_TRY(hipMemcpyAsync(P->h_stats, stats, sizeof(int64_t) * STATS_WORDS, hipMemcpyDeviceToHost, P->stream));
-    int64_t nnz = 0;
-    HIP_TRY(hipMemcpyAsync(&nnz, c_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
+    HIP_TRY(hipMemcpyAsync(P->h_stats + STATS_WORDS, c_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           P->stream));
+    SPG_TRY(host_wait(P));
+    const int64_t nnz = P->h_stats[STATS_WORDS];
     std::memcpy(P->num_counts, P->h_stats, sizeof(int64_t) * 4 * NBINS);
     std::memcpy(P->sym_counts, P->h_stats + STATS_SYM, sizeof(int64_t) * 3 * NBINS);
     int64_t tot = 0;
@@ -960,7 +976,7 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
         HIP_TRY(hipMemcpyAsync(P->h_stats, sstats, sizeof(int64_t) * NBINS, hipMemcpyDeviceToHost, P->stream));
         HIP_TRY(hipMemcpyAsync(P->h_stats + NBINS, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
                                P->stream));
-        HIP_TRY(hipStreamSynchronize(P->stream));
+        SPG_TRY(host_wait(P));
         SPG_TRY(check_row_products(bp, P->h_stats[NBINS]));
         std::memcpy(hint, P->h_stats, sizeof(hint));
     } else {
