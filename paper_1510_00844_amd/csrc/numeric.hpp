@@ -55,9 +55,31 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
     const typename S::acc_t a = S::load(A.val, p);
     const int64_t bs = B.rp[k], be = B.rp[k + 1];
     const int64_t off = c_rp.off(i) - bs;
-    for (int64_t q = bs + lane_id(); q < be; q += SPG_WAVE) {
-        c_col[off + q] = B.col[q];
-        if (c_val) S::store(c_val, off + q, S::mul(a, S::load(B.val, q)));
+    // four strides of the row loaded before any is stored, so the loads of
+    // a long B row overlap instead of waiting one stride at a time
+    constexpr int U = 4;
+    const int lane = lane_id();
+    for (int64_t q0 = bs; q0 < be; q0 += U * SPG_WAVE) {
+        int32_t cc[U];
+        typename S::acc_t vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + u * SPG_WAVE + lane;
+            cc[u] = 0;
+            vv[u] = S::zero();
+            if (q < be) {
+                cc[u] = B.col[q];
+                if (c_val) vv[u] = S::load(B.val, q);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + u * SPG_WAVE + lane;
+            if (q < be) {
+                c_col[off + q] = cc[u];
+                if (c_val) S::store(c_val, off + q, S::mul(a, vv[u]));
+            }
+        }
     }
 }
 
