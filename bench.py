@@ -796,9 +796,9 @@ def main():
             threads = len(os.sched_getaffinity(0))
         except Exception:
             pass
-        # the whole product, repeated until about 5 s of wall time have passed
+        # the whole product, repeated until about 12 s of wall time have passed
         runs, tc = 0, 0.0
-        while runs < 20 and (runs == 0 or tc < 5.0):
+        while runs < 60 and (runs == 0 or tc < 12.0):
             t0 = time.perf_counter()
             ref = oracle.spgemm(A, A, sr, nthreads=threads)
             tc += time.perf_counter() - t0
