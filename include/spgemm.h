@@ -101,9 +101,10 @@ typedef struct {
     int32_t rank_max_nnz;      /* numeric rows with a saved bitmap and at most this many outputs
                                   accumulate the whole row in one workgroup (capacities 4096, 8192,
                                   16384 as the LDS allows; below 4096: never) */
-    int32_t rank_block;        /* threads per workgroup of the whole-row rank accumulator: 512 or 1024
-                                  (1024: more loads in flight; capacity 16384 only when the LDS
-                                  allows it) */
+    int32_t rank_block;        /* threads per workgroup of the whole-row rank accumulator: 512 (the
+                                  default: shares the CUs better with the rank-chunk kernel beside it)
+                                  or 1024 (more loads in flight, faster alone; capacity 16384 only when
+                                  the LDS allows it) */
     int32_t serial_heavy;      /* the this-many bins with the most work run back to back on the plan's
                                   stream; the other bins are spread over the streams (0..16) */
     int32_t chunk_unroll;      /* gathers in flight per lane in the rank-chunk items (4 or 8) */

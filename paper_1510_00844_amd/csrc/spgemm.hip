@@ -325,7 +325,7 @@ extern "C" void spg_default_opts(spg_opts* o) {
     o->chunk_min_nnz = 0;  // = hash_max_nnz
     o->chunk_group = 32;
     o->rank_max_nnz = 8192;
-    o->rank_block = 1024;
+    o->rank_block = 512;
     o->chunk_unroll = 4;
     o->heap_max_lists = -1;  // off: slower than the hash tables on the workloads measured here
 }
