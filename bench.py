@@ -169,6 +169,26 @@ def trace_summary(path, top=25):
                                                     float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """GB/s (bytes read + written) of a plain device-to-device copy of
+    nbytes, timed with HIP events: the bandwidth a streaming kernel reaches
+    on this GPU, beside the nominal 8 TB/s."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2.0 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def copy_calibration():
     import torch
     nbytes = 256 << 20
@@ -450,9 +470,14 @@ def layered_modes(args, profile=False):
             plan.profile_reset()
         t_merge, M = _time(lambda: spg.spgemm_merge_layers(plan, "f64", layers), 3)
         assert M.nnz == C.nnz
+        # merge model: every layer read once, C written once (CSR bytes)
+        w_merge = sum(8.0 * (L.nrows + 1) + 12.0 * L.nnz for L in layers) + 8.0 * (M.nrows + 1) + 12.0 * M.nnz
         out["c%d" % c] = {"layers_ms": round(t_prod, 4), "merge_ms": round(t_merge, 4),
                           "gflops_layers": round(2.0 * flops / t_prod / 1e6, 3),
-                          "layer_nnz": sum(L.nnz for L in layers)}
+                          "layer_nnz": sum(L.nnz for L in layers),
+                          "merge_model_bytes": int(w_merge),
+                          "merge_model_gbs": round(w_merge / t_merge / 1e6, 2),
+                          "merge_model_frac": round(w_merge / t_merge / 1e6 / HBM_PEAK_GBS, 4)}
         if profile:
             out["c%d" % c]["layer_kernels"] = prod_kernels
             out["c%d" % c]["merge_kernels"] = kernel_table(plan, 4)
@@ -734,6 +759,11 @@ def main():
                                "symmetric permutation; C = A*A two-phase, plus-times FP64" % args.scale,
                    "m": A.nrows, "nnz_a": A.nnz, "flops": flops, "nnz_c": nnz, "seed": 2},
         "compulsory_bytes": int(A.nnz * 12 * 2 + (A.nrows + 1) * 16 + nnz * 12 + (A.nrows + 1) * 8),
+        # what the two-phase step issues beyond the one-pass model W: the
+        # symbolic pass's B row extents, B column gathers and row counts
+        "issued_bytes": int(W + 16.0 * A.nnz + 4.0 * flops + 8.0 * (A.nrows + 1)),
+        "model_bytes": int(W),
+        "copy_kernel_gbs": copy_bandwidth(),
         "hbm_model_gbs": round(W / (ms * 1e-3) / 1e9, 2),
         "hbm_model_frac": round(W / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,

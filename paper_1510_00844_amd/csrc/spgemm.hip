@@ -164,6 +164,7 @@ struct spg_plan_s {
     // Sparse SUMMA stages (child plans created on first use)
     spg_plan summa_p = nullptr, summa_s = nullptr;
     DevBuf sm_pos, sm_piece_rp, sm_p_rp, sm_p_col, sm_p_val, sm_s_rp, sm_s_col, sm_s_val, sm_c_rp, sm_c_pos;
+    DevBuf dc_pos;  // spg_dcsr_compress's row scan (apart from the stage state kept between calls)
     SummaState summa;
 
     // merge state
@@ -554,7 +555,7 @@ extern "C" spg_status spg_plan_destroy(spg_plan P) {
                       &P->sub_col, &P->sub_val, &P->sub_crp, &P->mlp_tmp, &P->sub_pos,
                       &P->mis_key, &P->mis_m1, &P->mis_cand, &P->mis_new, &P->mis_a1, &P->mis_flags, &P->mis_agg1,
                       &P->mis_ctr, &P->sm_pos, &P->sm_piece_rp, &P->sm_p_rp, &P->sm_p_col, &P->sm_p_val,
-                      &P->sm_s_rp, &P->sm_s_col, &P->sm_s_val, &P->sm_c_rp, &P->sm_c_pos})
+                      &P->sm_s_rp, &P->sm_s_col, &P->sm_s_val, &P->sm_c_rp, &P->sm_c_pos, &P->dc_pos})
         b->release();
     if (P->sub) spg_plan_destroy(P->sub);
     if (P->summa_p) spg_plan_destroy(P->summa_p);
@@ -1615,8 +1616,8 @@ extern "C" spg_status spg_dcsr_compress(spg_plan P, const spg_csr* A, int32_t* r
     SPG_TRY(P->small_i32.ensure(SMALL_WORDS * 4, "counters"));
     if (P->opts.validate && count_pass) SPG_TRY(validate_csr(P, A, "A"));
     const int64_t m = A->nrows;
-    SPG_TRY(nonempty_scan(P, A->row_ptr, m, P->sm_c_pos));
-    const int64_t* pos = P->sm_c_pos.as<int64_t>();
+    SPG_TRY(nonempty_scan(P, A->row_ptr, m, P->dc_pos));
+    const int64_t* pos = P->dc_pos.as<int64_t>();
     if (count_pass) return read_i64(P, pos + m, nzr);
     int64_t kept = 0;
     SPG_TRY(read_i64(P, pos + m, &kept));

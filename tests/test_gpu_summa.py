@@ -135,6 +135,41 @@ def test_summa_edge_cases(plan, stages, b):
     check_summa(plan, "f64", A, B, stages, b)
 
 
+def test_summa_fill_after_other_calls(plan):
+    """Calls on the plan between the count and the fill call (a compression,
+    an ordinary product) leave the stage state alone."""
+    M = synth.rmat(11, 16, synth.G500, seed=91)
+    A, B = synth.process_share(M, 2, 2, 1, 0, 1)
+    Ad = summa.compress(A)
+    import ctypes
+    dA, dB = _dcsr_dev(Ad, "f64"), to_dev(B, "f64")
+    a, bb = dA._c("f64"), dB._c("f64")
+    L = spg.lib()
+    nzr, nnz, snnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert L.spgemm_summa_local(plan.handle, 0, ctypes.byref(a), ctypes.byref(bb), 2, 64, None, None, None, None,
+                                ctypes.byref(nzr), ctypes.byref(nnz), ctypes.byref(snnz)) == 0
+    # other work on the same plan
+    spg.dcsr_compress(plan, to_dev(synth.random_csr(5000, 300, 0.01, 92, kind="f64"), "f64"))
+    X = to_dev(synth.random_csr(300, 300, 0.05, 93, kind="f64"), "f64")
+    spg.spgemm(plan, "f64", X, X)
+    ids = torch.empty(nzr.value, dtype=torch.int32, device=plan.device)
+    rp = torch.empty(nzr.value + 1, dtype=torch.int64, device=plan.device)
+    col = torch.empty(nnz.value, dtype=torch.int32, device=plan.device)
+    val = torch.empty(nnz.value, dtype=torch.float64, device=plan.device)
+    assert L.spgemm_summa_local(plan.handle, 0, ctypes.byref(a), ctypes.byref(bb), 2, 64,
+                                ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(rp.data_ptr()),
+                                ctypes.c_void_p(col.data_ptr()), ctypes.c_void_p(val.data_ptr()), None, None,
+                                None) == 0
+    ref, _ = summa.summa_local(Ad, B, 2, 64, "f64")
+    got = summa.DCSR(A.nrows, B.ncols, ids.cpu().numpy().astype(np.int64), rp.cpu().numpy(), col.cpu().numpy(),
+                     val.cpu().numpy())
+    assert np.array_equal(got.row_ids, ref.row_ids)
+    g, r = summa.expand(got), summa.expand(ref)
+    assert_same_structure(g, r)
+    U = oracle.spgemm(A, B, "f64")
+    assert_values(g, r, "f64", lambda: oracle.f64_check(A, B, U))
+
+
 def test_summa_no_inner_indices(plan):
     A = summa.DCSR(50, 0, np.zeros(0, np.int64), np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
     B = CSR(0, 30, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
