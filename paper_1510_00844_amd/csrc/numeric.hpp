@@ -5,7 +5,7 @@
 //   SMALL  <= 64 products: one wave per row; products sorted across the wave
 //          by (column, product order), equal columns folded left to right,
 //          which is ascending k (the order of Algorithm 1)
-//   HASH   workgroup per row: LDS open-addressing table sized >= 2 slots per
+//   HASH   workgroup per row: LDS open-addressing table sized >= 4/3 slots per
 //          output, semiring add by LDS atomics, then compaction and an LDS
 //          bitonic sort by column
 //   RANK   rows whose symbolic pass kept an n-bit bitmap: the bitmap is
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
             const int32_t j = x.col;
             const V v = S::mul(s_av[t], x.val);
             uint32_t h = hash_slot(j, LOG2T);
-            // the table has >= 2 slots per output of the symbolic count, so a
+            // the table has >= 4/3 slots per output of the symbolic count, so a
             // probe ends within T steps; the cap only guards inputs that
             // changed between the two phases
             for (int probes = 0; probes < T; ++probes) {
@@ -318,14 +318,18 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
         }
         __syncthreads();
     }
-    if (cnt > T / 2) cnt = T / 2;  // sort buffer capacity; only reached if inputs changed
-    // reuse the table: compacted values in tkey's bytes, sort keys in tval's
-    V* cval = reinterpret_cast<V*>(tkey);
+    // Full sort: (column, compact index) keys sorted in tval's bytes (up to
+    // T keys of 8 bytes); the sorted order gives each compact index its rank
+    // (in tkey's bytes), and every thread writes its own entries, whose
+    // values never left its registers, at their ranks.
     uint64_t* skey = reinterpret_cast<uint64_t*>(tval);
+    int32_t* rank_of = tkey;
+    int32_t posv[PER];
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-        if (rk[s] != EMPTY_KEY && pos < cnt) {
-            cval[pos] = rv[s];
+        posv[s] = -1;
+        if (rk[s] != EMPTY_KEY) {
+            posv[s] = pos;
             skey[pos] = ((uint64_t)(uint32_t)rk[s] << 32) | (uint64_t)pos;
             ++pos;
         }
@@ -335,11 +339,17 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     for (int t = cnt + threadIdx.x; t < P; t += NT) skey[t] = ~0ull;
     __syncthreads();
     block_bitonic_sort_u64<NT>(skey, P);
-    const int32_t nout = cnt < cnt_sym ? cnt : cnt_sym;
-    for (int t = threadIdx.x; t < nout; t += NT) {
-        uint64_t kk = skey[t];
-        c_col[o + t] = (int32_t)(kk >> 32);
-        if (c_val) S::store(c_val, o + t, cval[kk & 0xffffffffu]);
+    for (int t = threadIdx.x; t < cnt; t += NT) rank_of[(int32_t)(skey[t] & 0xffffffffu)] = t;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        if (posv[s] >= 0) {
+            const int32_t rank = rank_of[posv[s]];
+            if (rank < cnt_sym) {
+                c_col[o + rank] = rk[s];
+                if (c_val) S::store(c_val, o + rank, rv[s]);
+            }
+        }
     }
 }
 

@@ -49,7 +49,8 @@ __device__ inline int sym_bin(int64_t flops, int64_t annz, const BinParams& bp) 
     // once the row's products outnumber that, or once a hash table would not fit
     bool bitmap_cheaper = bp.dense_ok && flops * 32 >= bp.ncols;
     if (flops <= bp.hash_max_flops && !bitmap_cheaper) {  // larger rows: bitmap, in blocks if n is large
-        int lg = ceil_log2_i64(2 * flops);
+        // at most 3/4 of the slots in use (the row's distinct columns are at most its products)
+        int lg = ceil_log2_i64((4 * flops + 2) / 3);
         if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
         return BIN_HASH0 + (lg - HASH_MIN_LOG2);
     }
@@ -75,7 +76,7 @@ __device__ inline int num_bin(int64_t flops, int64_t annz, int64_t cnt, bool sym
     const bool chunks_ok = sym_dense && bp.chunk_counts;
     const int64_t hash_lim = chunks_ok ? bp.chunk_min_nnz : bp.hash_max_nnz;
     if (cnt <= hash_lim) {
-        int lg = ceil_log2_i64(2 * cnt);
+        int lg = ceil_log2_i64((4 * cnt + 2) / 3);  // at most 3/4 of the slots in use
         if (lg < HASH_MIN_LOG2) lg = HASH_MIN_LOG2;
         return BIN_HASH0 + (lg - HASH_MIN_LOG2);
     }

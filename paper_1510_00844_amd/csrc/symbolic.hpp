@@ -6,7 +6,7 @@
 //          sit one per lane and are sorted across the wave; the count is
 //          the number of run heads.
 //   HASH   : workgroup per row, open-addressing table of int32 keys in LDS
-//            (linear probing, >= 2 slots per product).
+//            (linear probing, >= 4/3 slots per product).
 //   DENSE  : workgroup per row, an n-bit bitmap in LDS (n <= 2^19), the
 //            structural part of the sparse accumulator of Section 3.
 #pragma once

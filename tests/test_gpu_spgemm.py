@@ -54,9 +54,9 @@ def _binned_matrices(seed=7):
     """A (m x K) whose rows cover every accumulator bin against an R-MAT B
     with hub rows: empty rows, one-entry rows, a few products, each hash
     size, and rows whose products exceed the hash limit."""
-    # B: the first 8192 rows of an R-MAT scale-16 matrix (65536 columns, so
-    # rows up to 2048 products stay in the hash bins and hub rows appear)
-    R = synth.rmat(16, 16, synth.G500, seed=seed)
+    # B: the first 8192 rows of an R-MAT scale-17 matrix (131072 columns, so
+    # rows up to 4096 products stay in the hash bins and hub rows appear)
+    R = synth.rmat(17, 16, synth.G500, seed=seed)
     K = 8192
     B = synth.CSR(K, R.ncols, R.row_ptr[:K + 1].copy(), R.col[:R.row_ptr[K]].copy(),
                   R.val[:R.row_ptr[K]].copy())
@@ -65,7 +65,10 @@ def _binned_matrices(seed=7):
     order = np.argsort(-blen)
     rows, cols = [], []
     r = 0
-    targets = [0, 1, 1, 2, 3, 5, 8, 12, 20, 40, 60, 100, 200, 400, 800, 1500, 3000, 6000, 12000, 30000, 60000]
+    # (the hash tables hold at most 3/4 of their slots: rows of 1900 and
+    # 3000 products take the 4096-slot table, below the 4096 where the
+    # bitmap starts)
+    targets = [0, 1, 1, 2, 3, 5, 8, 12, 20, 40, 60, 100, 200, 400, 800, 1500, 1900, 3000, 6000, 12000, 30000, 60000]
     for rep in range(6):
         for tf in targets:
             if tf == 0:
