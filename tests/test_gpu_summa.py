@@ -112,6 +112,24 @@ def test_summa_stages(plan, sr, stages, b):
     check_summa(plan, sr, _values(sr, A), _values(sr, B), stages, b)
 
 
+def test_summa_bool_without_values(plan):
+    """Boolean operands without value arrays (every stored entry true)."""
+    M = synth.rmat(12, 16, synth.G500, seed=95)
+    A, B = synth.process_share(M, 4, 2, 0, 3, 1)
+    A = synth.CSR(A.nrows, A.ncols, A.row_ptr, A.col, None)
+    B = synth.CSR(B.nrows, B.ncols, B.row_ptr, B.col, None)
+    Ad = summa.compress(A)
+    C, snnz = spg.spgemm_summa_local(plan, "bool", spg.DeviceDCSR.from_arrays(Ad.nrows, Ad.ncols, Ad.row_ids,
+                                                                            Ad.row_ptr, Ad.col, None),
+                                     spg.DeviceCSR.from_arrays(B.nrows, B.ncols, B.row_ptr, B.col, None), 4, 64)
+    ref, ref_snnz = summa.summa_local(Ad, B, 4, 64, "bool")
+    got = _host(C)
+    assert snnz == ref_snnz
+    assert np.array_equal(got.row_ids, ref.row_ids)
+    assert_same_structure(summa.expand(got), summa.expand(ref))
+    assert np.all(got.val == 1) and np.array_equal(got.val, ref.val)
+
+
 def test_summa_rows_without_products(plan):
     """Rows of A whose B rows are all empty give no result row: the DCSR
     result drops them."""
