@@ -115,7 +115,7 @@ typedef struct {
                                   (above the hash tables) may take the fused bitmap-and-rank kernel, up to
                                   rank_max_nnz and what the LDS holds; 0 = never (default: on this GPU
                                   the exact two-phase path is faster for such rows) */
-    int32_t heap_max_lists;    /* rows with at most this many A entries in the window and at most 512
+    int32_t heap_max_lists;    /* rows with at most this many A entries in the window and at most 384
                                   products are merged from their B rows by one wave (the heap bin,
                                   both passes; sorted output, ascending-k sums): 1..32; 0 = the
                                   default, -1 = never (the default: on the workloads measured the

@@ -20,7 +20,7 @@
 
 namespace spg {
 
-constexpr int KW_LMAX = 512;  // entries of one row a wave stages
+constexpr int KW_LMAX = 384;  // entries of one row a wave stages
 constexpr int KW_KMAX = 32;   // lists of one row
 constexpr int32_t KW_INF = 0x7fffffff;
 

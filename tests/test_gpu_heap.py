@@ -18,14 +18,15 @@ from util import assert_same_structure
 
 pytestmark = pytest.mark.gpu
 HEAP = spg.BIN_HEAP
+ROW_MAX = 384  # most products a heap-bin row takes (the entries one wave merges)
 
 
 def heap_rows(seed, m=3000, k_max=32, n=20000, K=6000):
     """A (m x K) with 2..k_max entries per row against B (K x n) whose rows
-    hold 0..60 entries, so rows have 65..512 products; plus rows built to
-    stress the merge: every list equal (each column k times), lists of one
-    entry, lists clustered in a narrow column range, empty B rows, and rows
-    at exactly k_max lists and 512 products."""
+    hold 0..60 entries, so rows have 65..ROW_MAX products; plus rows built
+    to stress the merge: every list equal (each column k times), lists of
+    one entry, lists clustered in a narrow column range, empty B rows, and
+    rows at exactly k_max lists."""
     rng = np.random.default_rng(seed)
     blen = rng.integers(0, 61, K)
     blen[:50] = 0  # empty B rows
@@ -54,8 +55,8 @@ def heap_rows(seed, m=3000, k_max=32, n=20000, K=6000):
             kk = int(rng.integers(2, k_max + 1))
             ks = rng.choice(np.arange(120, K), kk, replace=False)
         ks = np.sort(ks)[:k_max]
-        # keep the row at 65..512 products
-        while bl[ks].sum() > 512 and len(ks) > 2:
+        # keep the row at 65..ROW_MAX products
+        while bl[ks].sum() > ROW_MAX and len(ks) > 2:
             ks = ks[:-1]
         rows_a += [i] * len(ks)
         cols_a += ks.tolist()
@@ -78,7 +79,7 @@ def test_heap_bin_forced(sr, kmax):
     A, B = with_kind(A, sr), with_kind(B, sr)
     f = oracle.row_flops(A, B)
     annz = np.diff(A.row_ptr)
-    want = int(np.sum((annz > 1) & (f > 64) & (f <= 512) & (annz <= kmax)))
+    want = int(np.sum((annz > 1) & (f > 64) & (f <= ROW_MAX) & (annz <= kmax)))
     assert want > 1000
     p = spg.Plan(heap_max_lists=kmax)
     try:
@@ -91,7 +92,7 @@ def test_heap_bin_forced(sr, kmax):
             # ascending-k sums: bit for bit the oracle's on every row of the bin
             got = to_host(C)
             ref = oracle.spgemm(A, B, "f64")
-            heap = (annz > 1) & (f > 64) & (f <= 512) & (annz <= kmax)
+            heap = (annz > 1) & (f > 64) & (f <= ROW_MAX) & (annz <= kmax)
             sel = np.repeat(heap, np.diff(ref.row_ptr))
             assert got.val[sel].tobytes() == ref.val[sel].tobytes()
         # the same product through the hash tables

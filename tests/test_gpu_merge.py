@@ -97,10 +97,11 @@ def _layer(m, n, rows_lens, seed, sr="f64"):
 @pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
 def test_merge_edge_cases(plan, sr):
     """Empty layers, c = 1, rows in every merge bin (the wave k-way merge up
-    to 512 entries, rank placement up to 4096, the chunked dense path above),
+    to 384 entries, rank placement up to 4096, the chunked dense path above),
     bit for bit against the oracle's merge (ascending layer order)."""
     n = 20000
-    lens = [0, 1, 5, 30, 64, 65, 170, 171, 300, 511, 512, 513, 1500, 3000, 5000, 9000, 19000]
+    lens = [0, 1, 5, 30, 64, 65, 127, 128, 129, 170, 171, 300, 383, 384, 385, 511, 512, 513, 1500, 3000, 5000,
+            9000, 19000]
     layers_h = [_layer(len(lens), n, lens, 10 + l, sr) for l in range(3)]
     layers_h.append(_layer(len(lens), n, [0] * len(lens), 99, sr))  # an empty layer
     for sel in ([0], [3], [0, 1], [0, 1, 2, 3], [0, 3, 1]):
