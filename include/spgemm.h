@@ -210,8 +210,9 @@ spg_status spg_dcsr_expand(spg_plan plan, const spg_dcsr* A, int64_t* row_ptr);
  * *c_nnz (and, if not NULL, *stage_nnz, the entries of all block products,
  * the intermediate the merge reads), synchronizing.  Fill call, same A, B,
  * stages and b: c_row_ids (c_nzr entries), c_row_ptr (c_nzr+1), c_col and
- * c_val (c_nnz each; c_val may be NULL for the structure only); values are
- * those read by the count call.  SPG_ERR_STATE if the fill call does not
+ * c_val (c_nnz each; c_val may be NULL for the structure only; arrays of no
+ * entries may be NULL).  A's and B's values must not change between the two
+ * calls (either call may read them).  SPG_ERR_STATE if the fill call does not
  * match the last count call on the plan; SPG_ERR_INDEX_RANGE above 2^22
  * row pieces (a piece is the part of a row inside one block). */
 spg_status spgemm_summa_local(spg_plan plan, spg_semiring sr, const spg_dcsr* A, const spg_csr* B,
