@@ -142,6 +142,41 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
     }
 }
 
+// Sorts the n <= N keys keys[off, off + n) of the calling thread ascending,
+// in registers: unused places hold the largest key, a bitonic network of
+// compile-time comparators (a min and a max each) orders them, and the first
+// n are written back.  Reads stay inside [0, T).
+template <int N>
+__device__ inline void bucket_sort_net(uint32_t* keys, int32_t off, int32_t n, int32_t T) {
+    uint32_t a[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        const int32_t x = off + u < T - 1 ? off + u : T - 1;
+        const uint32_t v = keys[x];
+        a[u] = u < n ? v : 0xffffffffu;
+    }
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t lo = a[i] < a[l] ? a[i] : a[l];
+                    const uint32_t hi = a[i] < a[l] ? a[l] : a[i];
+                    const bool up = (i & k) == 0;
+                    a[i] = up ? lo : hi;
+                    a[l] = up ? hi : lo;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+        if (u < n) keys[off + u] = a[u];
+}
+
 // cnt_out (optional) receives each row's output count; a count above the
 // slot c_rp.count(i) means the slot overflowed (only then is the output
 // incomplete).
@@ -156,7 +191,10 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
     constexpr int PER = T / NT;  // table slots owned by a thread during compaction
     static_assert(PER >= 1, "table smaller than block");
     __shared__ int32_t tkey[T];
-    __shared__ V tval[T];
+    // 8 bytes a slot whatever the value type: the full sort below keeps up
+    // to T keys of 8 bytes there
+    __shared__ uint64_t tval_store[T];
+    V* tval = reinterpret_cast<V*>(tval_store);
     __shared__ ProductLds<NT> L;
     __shared__ int32_t red[NT / SPG_WAVE + 1];
     __shared__ int32_t mm[2 * (NT / SPG_WAVE)];
@@ -265,19 +303,26 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
         }
         return;
     }
-    // Wide spans: NT buckets of equal column width, one per thread.  The
-    // entries are counted per bucket, placed bucket by bucket, and each thread
-    // sorts its own bucket (insertion sort); then the row is written in order.
-    // Falls back to the full sort below when some bucket holds more than 32.
+    // Wide spans: NT buckets of (nearly) equal column width, one per thread.
+    // The entries are counted per bucket, placed bucket by bucket, and each
+    // thread sorts its own bucket (insertion sort); then the row is written in
+    // order.  Falls back to the full sort below when some bucket holds more
+    // than 32.  The bucket of a column is (column - kmin) * NT / span in FP32,
+    // truncated and clamped to NT - 1: every step of that is monotone, so the
+    // buckets follow column order, and it costs a multiply where an integer
+    // division by the width would cost a few dozen instructions per entry.
     if (cnt <= T) {
-        const int64_t span = (int64_t)kmax - kmin + 1;
-        const int32_t width = (int32_t)((span + NT - 1) / NT);
+        const float bscale = (float)NT / (float)((int64_t)kmax - kmin + 1);
+        auto bucket_of = [&](int32_t key) {
+            const int32_t b = (int32_t)((float)(uint32_t)(key - kmin) * bscale);
+            return b < NT - 1 ? b : NT - 1;
+        };
         s_bucket[threadIdx.x] = 0;
         __syncthreads();
         int32_t bl[PER];
 #pragma unroll
         for (int s = 0; s < PER; ++s)
-            bl[s] = rk[s] != EMPTY_KEY ? atomicAdd(&s_bucket[(rk[s] - kmin) / width], 1) : 0;
+            bl[s] = rk[s] != EMPTY_KEY ? atomicAdd(&s_bucket[bucket_of(rk[s])], 1) : 0;
         __syncthreads();
         const int32_t mycnt = s_bucket[threadIdx.x];
         int32_t bmin = mycnt, bmax = mycnt;
@@ -287,10 +332,40 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
             const int32_t boff = block_exclusive_scan<NT, int32_t>(mycnt, &tot, red);
             s_bucket[threadIdx.x] = boff;
             __syncthreads();
+            const int32_t nout = cnt < cnt_sym ? cnt : cnt_sym;
+            // Columns that fit beside a slot index in 32 bits: each entry
+            // becomes the key (column - kmin) << LOG2T | slot, the values stay
+            // in the table, and every thread sorts its bucket's keys in
+            // registers with a sorting network (two instructions per
+            // comparator, no LDS round trips).  Buckets of 17 to 32 take a
+            // network only in the kernels of 16 slots per thread, where they
+            // are common; elsewhere its registers would cost waves.
+            constexpr int NET_MAX = PER >= 16 ? 32 : 16;
+            if (bmax <= NET_MAX && cnt > 0 && (int64_t)kmax - kmin < (1ll << (32 - LOG2T))) {
+#pragma unroll
+                for (int s = 0; s < PER; ++s) {
+                    if (rk[s] != EMPTY_KEY) {
+                        const int32_t q = s_bucket[bucket_of(rk[s])] + bl[s];
+                        tkey[q] = (int32_t)(((uint32_t)(rk[s] - kmin) << LOG2T) | (uint32_t)(threadIdx.x * PER + s));
+                    }
+                }
+                __syncthreads();
+                uint32_t* pk = reinterpret_cast<uint32_t*>(tkey);
+                if (bmax <= 8) bucket_sort_net<8>(pk, boff, mycnt, T);
+                else if (NET_MAX == 16 || bmax <= 16) bucket_sort_net<16>(pk, boff, mycnt, T);
+                else bucket_sort_net<NET_MAX>(pk, boff, mycnt, T);
+                __syncthreads();
+                for (int t = threadIdx.x; t < nout; t += NT) {
+                    const uint32_t key = (uint32_t)tkey[t];
+                    c_col[o + t] = kmin + (int32_t)(key >> LOG2T);
+                    if (c_val) S::store(c_val, o + t, tval[key & (T - 1)]);
+                }
+                return;
+            }
 #pragma unroll
             for (int s = 0; s < PER; ++s) {
                 if (rk[s] != EMPTY_KEY) {
-                    const int32_t q = s_bucket[(rk[s] - kmin) / width] + bl[s];
+                    const int32_t q = s_bucket[bucket_of(rk[s])] + bl[s];
                     tkey[q] = rk[s];
                     tval[q] = rv[s];
                 }
@@ -309,7 +384,6 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
                 tval[y + 1] = vx;
             }
             __syncthreads();
-            const int32_t nout = cnt < cnt_sym ? cnt : cnt_sym;
             for (int t = threadIdx.x; t < nout; t += NT) {
                 c_col[o + t] = tkey[t];
                 if (c_val) S::store(c_val, o + t, tval[t]);
@@ -318,11 +392,11 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
         }
         __syncthreads();
     }
-    // Full sort: (column, compact index) keys sorted in tval's bytes (up to
-    // T keys of 8 bytes); the sorted order gives each compact index its rank
-    // (in tkey's bytes), and every thread writes its own entries, whose
-    // values never left its registers, at their ranks.
-    uint64_t* skey = reinterpret_cast<uint64_t*>(tval);
+    // Full sort: (column, compact index) keys sorted in the value storage
+    // (up to T keys of 8 bytes); the sorted order gives each compact index
+    // its rank (in tkey's bytes), and every thread writes its own entries,
+    // whose values never left its registers, at their ranks.
+    uint64_t* skey = tval_store;
     int32_t* rank_of = tkey;
     int32_t posv[PER];
 #pragma unroll

@@ -393,3 +393,90 @@ def test_ssca_class(plan, sr):
     if sr != "f64":
         A = with_kind(A, sr)
     check_full_vs_oracle(run(plan, sr, A, A), A, A, sr)
+
+
+# table size -> threads of the numeric hash kernel for that size
+_HASH_NT = {7: 64, 8: 64, 9: 64, 10: 128, 11: 256, 12: 256, 13: 512}
+
+
+def _order_path(cols):
+    """How the numeric hash kernel orders a row with these distinct sorted
+    output columns: by bitmap rank (narrow span), by per-thread column
+    buckets sorted in registers (at most 8, 16, or -- with 16 table slots per
+    thread -- 32 per bucket, columns that fit beside a slot index in 32
+    bits), by buckets sorted in place (at most 32), or by the full sort.  The
+    bucket of a column is (column - min) * threads / span in FP32, as in the
+    kernel."""
+    cnt = cols.size
+    lg = max(7, int(np.ceil(np.log2((4 * cnt + 2) // 3))))
+    T, NT = 1 << lg, _HASH_NT[lg]
+    kmin, kmax = int(cols[0]), int(cols[-1])
+    nw = ((kmax - kmin) >> 5) + 1
+    if nw <= T and nw <= 8 * cnt + 64:
+        return "bitmap"
+    scale = np.float32(NT) / np.float32(kmax - kmin + 1)
+    b = np.minimum(((cols - kmin).astype(np.float32) * scale).astype(np.int64), NT - 1)
+    bmax = int(np.bincount(b).max())
+    if bmax > 32:
+        return "full_sort"
+    net_max = 32 if T // NT >= 16 else 16
+    if bmax <= net_max and kmax - kmin < (1 << (32 - lg)):
+        return "net8" if bmax <= 8 else ("net16" if bmax <= 16 else "net32")
+    return "in_place"
+
+
+def _hash_order_rows(n, specs, seed):
+    """A (len(specs) rows) times B (one entry per row, at a chosen column):
+    row r of A holds f_r consecutive B rows, so C(r,:) has exactly the
+    chosen columns.  A tenth of each row's products repeat a column of the
+    row, so equal columns are summed.  Patterns: "uniform" over [0, n),
+    "narrow" inside a window of 4 f columns, "clusterW": W consecutive
+    columns plus uniform ones."""
+    rng = np.random.default_rng(seed)
+    arow, bcol, rows_cols = [], [], []
+    for r, (f, pat) in enumerate(specs):
+        nd = f - f // 10
+        if pat == "uniform":
+            cols = rng.choice(n, nd, replace=False)
+        elif pat == "narrow":
+            cols = int(rng.integers(0, n - 4 * f)) + rng.choice(4 * f, nd, replace=False)
+        else:
+            w = int(pat[len("cluster"):])
+            start = int(rng.integers(0, n - w))
+            cols = np.unique(np.concatenate([start + np.arange(w), rng.choice(n, nd - w, replace=False)]))
+        cols = np.unique(cols)
+        allc = np.concatenate([cols, rng.choice(cols, f - cols.size)])
+        rng.shuffle(allc)
+        arow += [r] * allc.size
+        bcol += allc.tolist()
+        rows_cols.append(cols)
+    k = len(bcol)
+    A = CSR(len(specs), k, np.concatenate([[0], np.cumsum([f for f, _ in specs])]).astype(np.int64),
+            np.arange(k, dtype=np.int32), rng.random(k) + 0.5)
+    B = CSR(k, n, np.arange(k + 1, dtype=np.int64), np.asarray(bcol, dtype=np.int32), rng.random(k) + 0.5)
+    return A, B, rows_cols
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_hash_row_orders(plan, sr):
+    """Rows of the hash bins reaching every way the numeric hash kernel
+    puts a row in column order (bitmap rank, register sorting networks of 8,
+    16 and 32, in-place bucket sort, full sort; columns too far apart to pack
+    beside a slot index), all against the oracle."""
+    specs = []
+    for f in (100, 150, 300, 700, 1400, 2500):
+        specs += [(f, "uniform"), (f, "narrow"), (f, "cluster20"), (f, "cluster28"), (f, "cluster40"),
+                  (f, "cluster70")]
+    seen = set()
+    for n, seed, sp in ((1 << 18, 71, specs), (1 << 21, 72, [(f, "uniform") for f in (1400, 2000, 2500, 2900)]
+                                                                         + [(100, "cluster20"), (300, "cluster28")])):
+        A, B, rows_cols = _hash_order_rows(n, sp, seed)
+        paths = [_order_path(c) for c in rows_cols]
+        seen |= set(paths)
+        print("case hash orders n=%d sr=%s paths=%s" % (n, sr, sorted(set(paths))), flush=True)
+        A, B = (A, B) if sr == "f64" else (with_kind(A, sr, seed), with_kind(B, sr, seed))
+        C = run(plan, sr, A, B)
+        st = plan.stats()
+        assert sum(st["num_rows"][3:11]) == A.nrows, "rows outside the hash bins"
+        check_full_vs_oracle(C, A, B, sr)
+    assert seen >= {"bitmap", "net8", "net16", "net32", "in_place", "full_sort"}, seen
