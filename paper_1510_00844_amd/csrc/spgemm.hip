@@ -967,18 +967,19 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
     // operands are seen (exact), else those of the last call with them
     // (checked against the real counts at the final readback).  A graph
     // capture (frozen) reuses the eager call's counts.
-    int64_t hint[NBINS];
+    // hint[b] = rows of bin b, hint[NBINS + b] = their products.
+    int64_t hint[2 * NBINS];
     bool exact = true;
     const bool known = P->bm_rows >= 0 && P->bm_sig == sg && bp.dense_ok && c_nnz != nullptr && !fresh;
     if (P->frozen || known) {
         std::memcpy(hint, P->sym_counts, sizeof(hint));
         exact = P->frozen;
     } else if (m > 0) {
-        HIP_TRY(hipMemcpyAsync(P->h_stats, sstats, sizeof(int64_t) * NBINS, hipMemcpyDeviceToHost, P->stream));
-        HIP_TRY(hipMemcpyAsync(P->h_stats + NBINS, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
+        HIP_TRY(hipMemcpyAsync(P->h_stats, sstats, sizeof(hint), hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipMemcpyAsync(P->h_stats + 2 * NBINS, stats + 4 * NBINS, sizeof(int64_t), hipMemcpyDeviceToHost,
                                P->stream));
         SPG_TRY(host_wait(P));
-        SPG_TRY(check_row_products(bp, P->h_stats[NBINS]));
+        SPG_TRY(check_row_products(bp, P->h_stats[2 * NBINS]));
         std::memcpy(hint, P->h_stats, sizeof(hint));
     } else {
         std::memset(hint, 0, sizeof(hint));
@@ -1038,18 +1039,25 @@ static spg_status symbolic_pass(spg_plan P, spg_semiring sr, const spg_csr* A, c
                 });
             }, true, pipelined(P, b, 4)));
         }
-        // the other bins, by decreasing work, round robin over the helper
-        // streams (the bitmap rows keep the plan's stream)
+        // the other bins, by decreasing work, each on the helper stream with
+        // the least work so far (the bitmap rows keep the plan's stream)
         std::vector<int> order;
         for (int bb = BIN_SMALL; bb < BIN_DENSE_PAR; ++bb)
             if (hint[bb] > 0) order.push_back(bb);
         if (hint[BIN_HEAP] > 0) order.push_back(BIN_HEAP);
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-            return hint[NBINS + x] + 32 * hint[x] > hint[NBINS + y] + 32 * hint[y];
-        });
-        int k = 0;
+        auto work = [&](int x) { return (double)hint[NBINS + x] + 32.0 * (double)hint[x]; };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+        double aux_load[NAUX] = {};
         for (int bb : order) {
-            P->cur = nstreams > 1 ? P->aux[k++ % (nstreams - 1)] : P->stream;
+            if (nstreams > 1) {
+                int s = 0;
+                for (int k = 1; k < nstreams - 1; ++k)
+                    if (aux_load[k] < aux_load[s]) s = k;
+                aux_load[s] += work(bb);
+                P->cur = P->aux[s];
+            } else {
+                P->cur = P->stream;
+            }
             if (bb == BIN_HEAP) {
                 SPG_TRY(sym_heap_launch(P, a, b, BinRef{sstats, lists, BIN_HEAP}, hint[bb], cnt));
             } else if (bb == BIN_SMALL) {
