@@ -318,4 +318,63 @@ __device__ inline uint32_t hash_slot(int32_t key, int log2t) {
     return ((uint32_t)key * 2654435761u) >> (32 - log2t);
 }
 
+// Sorts the n <= N keys keys[off, off + n) of the calling thread ascending,
+// in registers: unused places hold the largest key, a bitonic network of
+// compile-time comparators (a min and a max each) orders them, and the first
+// n are written back.  Reads stay inside [0, T).
+template <int N>
+__device__ inline void bucket_sort_net(uint32_t* keys, int32_t off, int32_t n, int32_t T) {
+    uint32_t a[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        const int32_t x = off + u < T - 1 ? off + u : T - 1;
+        const uint32_t v = keys[x];
+        a[u] = u < n ? v : 0xffffffffu;
+    }
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t lo = a[i] < a[l] ? a[i] : a[l];
+                    const uint32_t hi = a[i] < a[l] ? a[l] : a[i];
+                    const bool up = (i & k) == 0;
+                    a[i] = up ? lo : hi;
+                    a[l] = up ? hi : lo;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+        if (u < n) keys[off + u] = a[u];
+}
+
+// Sorts keys[0, P) ascending (P a power of two) with the calling wave
+// alone: a bitonic network whose compare-exchanges the lanes share, one
+// stage between wave-level LDS fences.
+__device__ inline void wave_lds_bitonic_u32(uint32_t* keys, int P) {
+    const int lane = lane_id();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P / 2; t += SPG_WAVE) {
+                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // bit j of i clear
+                const int l = i | j;
+                const uint32_t x = keys[i], y = keys[l];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    keys[i] = y;
+                    keys[l] = x;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
 }  // namespace spg

@@ -3,6 +3,12 @@
 // output is the sorted union of the c sorted segments layer_l(i,:), with
 // values of equal columns combined in ascending layer order.  The paper
 // merges with a heap per thread over a split of the column range; here:
+//   SORT   (more than 8 layers) rows of 65 ... MS_LMAX entries whose columns
+//          span less than 2^(32 - MS_XBITS): one wave per row; every entry
+//          becomes a 32-bit key (column - min, then its index in the
+//          layer-major order), the keys go to 64 column buckets (one per
+//          lane) and each lane sorts its bucket in registers; equal columns
+//          are then adjacent in ascending layer order
 //   WAVE   rows of at most KW_LMAX entries over at most 8 layers: one
 //          wave per row, the column range split over the 64 lanes and each
 //          lane merging its range of the c segments (kway.hpp), staged in LDS
@@ -35,12 +41,21 @@ struct LayerSet {
 
 // merge bins by total row length L over the layers
 constexpr int MBIN_EMPTY = 0, MBIN_WAVE = 1, MBIN_SMALL = 2, MBIN_R256 = 3, MBIN_R1K = 4, MBIN_R4K = 5,
-              MBIN_DENSE = 6;
-constexpr int MBINS = 7;
+              MBIN_DENSE = 6, MBIN_SORT = 7;
+constexpr int MBINS = 8;
+
+// the bucket-sort bin: entries per row, bits of a staged index, column span
+constexpr int MS_LMAX = 512;
+constexpr int MS_XBITS = 9;
+constexpr int64_t MS_SPAN_MAX = 1ll << (32 - MS_XBITS);
+static_assert((MS_LMAX & (MS_LMAX - 1)) == 0 && MS_LMAX <= (1 << MS_XBITS),
+              "the whole-row sort pads to a power of two inside the key array");
 constexpr int MERGE_LDS_MAX = 4096;
 
 // The wave k-way merge costs O(c) instructions per output (the smallest of c
-// heads each step): it wins for few layers; more layers take the rank paths.
+// heads each step): it wins for few layers (with 4 layers it is 1.6 times
+// as fast as the bucket sort); more layers take the bucket sort and rank
+// paths.
 constexpr int MERGE_KWAY_MAX_LAYERS = 8;
 
 __device__ inline int merge_bin(int64_t L, int c) {
@@ -68,6 +83,18 @@ __global__ void __launch_bounds__(256) k_merge_rowinfo(int64_t m, int32_t c, Lay
         for (int l = 0; l < c; ++l) L += layers.d[l].rp[i + 1] - layers.d[l].rp[i];
         total_len[i] = L;
         int b = merge_bin(L, c);
+        if (c > MERGE_KWAY_MAX_LAYERS && L > SPG_WAVE && L <= MS_LMAX) {  // the bucket sort, if the columns pack
+            int32_t mn = 0x7fffffff, mx = -1;
+            for (int l = 0; l < c; ++l) {
+                const int64_t rs = layers.d[l].rp[i], re = layers.d[l].rp[i + 1];
+                if (re > rs) {
+                    const int32_t a = layers.d[l].col[rs], z = layers.d[l].col[re - 1];
+                    mn = a < mn ? a : mn;
+                    mx = z > mx ? z : mx;
+                }
+            }
+            if ((int64_t)mx - mn < MS_SPAN_MAX) b = MBIN_SORT;
+        }
         bin[i] = (uint8_t)b;
         atomicAdd(&s_hist[b], 1);
         atomicAdd((unsigned long long*)&s_len[b], (unsigned long long)L);
@@ -106,6 +133,158 @@ __global__ void __launch_bounds__(256) k_merge_kway(int32_t c, LayerSet layers, 
                                                                    FILL ? out_rp[i] : 0);
         if (!FILL && lane == 0) cnt[i] = got;
         wave_lds_sync();  // the staged row is read before the next one overwrites it
+    }
+}
+
+// Per-wave LDS of the bucket-sort merge: the row's keys, its values by
+// staged index (fill pass), the bucket counters.
+template <typename V, bool FILL>
+struct MsLds {
+    uint32_t key[MS_LMAX];
+    V val[FILL ? MS_LMAX : 1];
+    int32_t bcnt[SPG_WAVE];
+};
+
+// One wave per row of the SORT bin (4 per workgroup).  Entry x of the flat
+// order (layer 0's segment, then layer 1's, ...) gets the key
+// (column - cmin) << MS_XBITS | x, so keys order by column and equal columns
+// by layer.  The keys are counted into 64 buckets of equal column width
+// (bucket = (column - cmin) * 64 / span in FP32, monotone), placed bucket by
+// bucket, and every lane sorts its own bucket with a register network; a
+// row whose largest bucket holds more than 16 is sorted whole by the wave
+// (a larger network would cost registers, and so waves, on every row).
+// Runs of equal columns are then folded in key order.  cnt != nullptr: count
+// pass; otherwise fill pass at out_rp.
+template <int SR, bool FILL>
+__global__ void __launch_bounds__(256) k_merge_sort(int32_t c, LayerSet layers, BinRef ref, int64_t* cnt,
+                                                    const int64_t* out_rp, int32_t* out_col, void* out_val) {
+    typedef Sr<SR> S;
+    typedef typename S::acc_t V;
+    constexpr int NU = MS_LMAX / SPG_WAVE;
+    constexpr uint32_t XMASK = (1u << MS_XBITS) - 1;
+    __shared__ MsLds<V, FILL> lds[4];
+    MsLds<V, FILL>& W = lds[threadIdx.x >> 6];
+    const int32_t* rows;
+    int64_t n;
+    ref.locate(rows, n);
+    const int lane = lane_id();
+    int top = 1;  // search width over the layers
+    while (top < c) top <<= 1;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n; r += (int64_t)gridDim.x * 4) {
+        const int64_t i = rows[r];
+        // lane l < c: layer l's segment, its first and last column
+        int64_t rs = 0;
+        int32_t len = 0, cmin = 0x7fffffff, cmax = -1;
+        const int32_t* colp = nullptr;
+        const void* valp = nullptr;
+        if (lane < c) {
+            colp = layers.d[lane].col;
+            valp = layers.d[lane].val;
+            rs = layers.d[lane].rp[i];
+            len = (int32_t)(layers.d[lane].rp[i + 1] - rs);
+            if (len > 0) {
+                cmin = colp[rs];
+                cmax = colp[rs + len - 1];
+            }
+        }
+        const int32_t incl = wave_inclusive_scan_add(len);
+        const int32_t soff = incl - len;
+        const int32_t L = __builtin_amdgcn_readlane(incl, SPG_WAVE - 1);
+#pragma unroll
+        for (int d = SPG_WAVE / 2; d > 0; d >>= 1) {
+            const int32_t a = lane_xor(cmin, d), b = lane_xor(cmax, d);
+            cmin = a < cmin ? a : cmin;
+            cmax = b > cmax ? b : cmax;
+        }
+        const float bscale = (float)SPG_WAVE / (float)((int64_t)cmax - cmin + 1);
+        W.bcnt[lane] = 0;
+        wave_lds_sync();
+        // stage: entry x = u * 64 + lane lies in the last layer whose
+        // segment starts at or before x (empty segments share the start of
+        // the next one)
+        uint32_t ck[NU];
+        int32_t cbs[NU];  // bucket << 16 | place in the bucket
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            if (u * SPG_WAVE >= L) break;
+            const int32_t x = u * SPG_WAVE + lane;
+            int l = 0;
+            for (int step = top >> 1; step > 0; step >>= 1) {
+                const int cand = l + step;
+                const int32_t so = __shfl(soff, cand < SPG_WAVE ? cand : SPG_WAVE - 1, SPG_WAVE);
+                if (cand < c && so <= x) l = cand;
+            }
+            const int32_t lo = __shfl(soff, l, SPG_WAVE);
+            const int64_t st = __shfl((long long)rs, l, SPG_WAVE);
+            const int32_t* cp = (const int32_t*)__shfl((long long)(intptr_t)colp, l, SPG_WAVE);
+            const void* vp = FILL ? (const void*)__shfl((long long)(intptr_t)valp, l, SPG_WAVE) : nullptr;
+            if (x < L) {
+                const int64_t q = st + (x - lo);
+                const uint32_t rel = (uint32_t)(cp[q] - cmin);
+                int32_t b = (int32_t)((float)rel * bscale);
+                b = b < SPG_WAVE - 1 ? b : SPG_WAVE - 1;
+                ck[u] = (rel << MS_XBITS) | (uint32_t)x;
+                cbs[u] = (b << 16) | atomicAdd(&W.bcnt[b], 1);
+                if constexpr (FILL) {
+                    // no value array: structure-only output (booleans: all true)
+                    W.val[x] = (vp || SR == SR_BOOL) ? S::load(vp, q) : S::zero();
+                }
+            }
+        }
+        wave_lds_sync();
+        const int32_t mycnt = W.bcnt[lane];
+        const int32_t bmax = wave_reduce_max(mycnt);
+        const int32_t boff = wave_inclusive_scan_add(mycnt) - mycnt;
+        wave_lds_sync();  // every lane has read its count
+        W.bcnt[lane] = boff;
+        wave_lds_sync();
+        if (bmax <= 16) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                if (u * SPG_WAVE >= L) break;
+                if (u * SPG_WAVE + lane < L) W.key[W.bcnt[cbs[u] >> 16] + (cbs[u] & 0xffff)] = ck[u];
+            }
+            wave_lds_sync();
+            if (bmax <= 8) bucket_sort_net<8>(W.key, boff, mycnt, MS_LMAX);
+            else bucket_sort_net<16>(W.key, boff, mycnt, MS_LMAX);
+        } else {
+            int P = SPG_WAVE;
+            while (P < L) P <<= 1;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int32_t x = u * SPG_WAVE + lane;
+                if (x < L) W.key[x] = ck[u];
+                else if (x < P) W.key[x] = 0xffffffffu;
+            }
+            wave_lds_sync();
+            wave_lds_bitonic_u32(W.key, P);
+        }
+        wave_lds_sync();
+        // runs of equal columns: each lane takes a contiguous range of
+        // sorted positions and owns the runs that start there
+        const int per = (L + SPG_WAVE - 1) / SPG_WAVE;
+        const int q0 = lane * per < L ? lane * per : L;
+        const int q1 = q0 + per < L ? q0 + per : L;
+        int32_t heads = 0;
+        for (int q = q0; q < q1; ++q) heads += (q == 0 || (W.key[q] >> MS_XBITS) != (W.key[q - 1] >> MS_XBITS)) ? 1 : 0;
+        if constexpr (!FILL) {
+            const int32_t tot = wave_reduce_add(heads);
+            if (lane == 0) cnt[i] = tot;
+        } else {
+            int64_t o = out_rp[i] + (wave_inclusive_scan_add(heads) - heads);
+            for (int q = q0; q < q1; ++q) {
+                const uint32_t kq = W.key[q];
+                if (q == 0 || (kq >> MS_XBITS) != (W.key[q - 1] >> MS_XBITS)) {
+                    V acc = W.val[kq & XMASK];
+                    for (int y = q + 1; y < L && (W.key[y] >> MS_XBITS) == (kq >> MS_XBITS); ++y)
+                        acc = S::add(acc, W.val[W.key[y] & XMASK]);
+                    out_col[o] = cmin + (int32_t)(kq >> MS_XBITS);
+                    if (out_val) S::store(out_val, o, acc);
+                    ++o;
+                }
+            }
+        }
+        wave_lds_sync();  // the row's LDS is read before the next row overwrites it
     }
 }
 

@@ -142,41 +142,6 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
     }
 }
 
-// Sorts the n <= N keys keys[off, off + n) of the calling thread ascending,
-// in registers: unused places hold the largest key, a bitonic network of
-// compile-time comparators (a min and a max each) orders them, and the first
-// n are written back.  Reads stay inside [0, T).
-template <int N>
-__device__ inline void bucket_sort_net(uint32_t* keys, int32_t off, int32_t n, int32_t T) {
-    uint32_t a[N];
-#pragma unroll
-    for (int u = 0; u < N; ++u) {
-        const int32_t x = off + u < T - 1 ? off + u : T - 1;
-        const uint32_t v = keys[x];
-        a[u] = u < n ? v : 0xffffffffu;
-    }
-#pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t lo = a[i] < a[l] ? a[i] : a[l];
-                    const uint32_t hi = a[i] < a[l] ? a[l] : a[i];
-                    const bool up = (i & k) == 0;
-                    a[i] = up ? lo : hi;
-                    a[l] = up ? hi : lo;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < N; ++u)
-        if (u < n) keys[off + u] = a[u];
-}
-
 // cnt_out (optional) receives each row's output count; a count above the
 // slot c_rp.count(i) means the slot overflowed (only then is the output
 // incomplete).

@@ -1311,6 +1311,16 @@ static spg_status merge_launch(spg_plan P, int32_t c, const LayerSet& ls, int64_
         if (bb == MBIN_WAVE) {
             if (cnt) SPG_TRY((merge_kway_launch<SR, false>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
             else SPG_TRY((merge_kway_launch<SR, true>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
+        } else if (bb == MBIN_SORT) {
+            if (cnt) {
+                SPG_TRY(launch(P, "merge_sort_count", [&] {
+                    k_merge_sort<SR, false><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
+                }));
+            } else {
+                SPG_TRY(launch(P, "merge_sort", [&] {
+                    k_merge_sort<SR, true><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
+                }));
+            }
         } else if (bb == MBIN_SMALL) {
             SPG_TRY(launch(P, "merge_small", [&] {
                 k_merge_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);

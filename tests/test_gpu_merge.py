@@ -130,3 +130,49 @@ def test_merge_many_layers(plan, c):
     got = to_host(M)
     assert_same_structure(got, ref)
     assert got.val.tobytes() == ref.val.tobytes()
+
+
+def _layers_from_rows(n, row_cols, c, seed, sr="f64"):
+    """c layers whose row i together hold the columns row_cols[i] (each
+    column goes to 1..3 random layers, so many columns are shared)."""
+    rng = np.random.default_rng(seed)
+    per = [([], []) for _ in range(c)]
+    for i, cols in enumerate(row_cols):
+        for j in cols:
+            for l in rng.choice(c, int(rng.integers(1, min(3, c) + 1)), replace=False):
+                per[l][0].append(i)
+                per[l][1].append(int(j))
+    out = []
+    for l, (rr, cc) in enumerate(per):
+        vals = {"f64": rng.random(len(rr)), "i64": rng.integers(-5, 6, len(rr)),
+                "bool": (rng.random(len(rr)) < 0.7).astype(np.uint8)}[sr]
+        out.append(synth.canonical_from_coo(len(row_cols), n, rr, cc, vals, dup="first"))
+    return out
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+@pytest.mark.parametrize("c", [2, 4, 16])
+def test_merge_sort_bin_shapes(plan, sr, c):
+    """Rows of the bucket-sort merge bin (65..512 entries over the layers)
+    with uniform columns (buckets of at most 8 or 16, sorted in registers),
+    with a band of columns next to a few far ones (larger buckets: the whole
+    row is sorted by the wave), and rows whose columns span 2^23 or more
+    (left to the other merge paths), all bit for bit against the oracle's
+    merge."""
+    rng = np.random.default_rng(500 + c)
+    n = (1 << 24) + 5
+    rows = []
+    for target in (30, 60, 100, 170, 250):
+        rows.append(np.unique(rng.choice(1 << 20, target, replace=False)))          # uniform
+        for band in (20, 28, 45, 160):                                             # clustered
+            start = int(rng.integers(0, (1 << 20) - band))
+            far = rng.choice(1 << 20, max(1, target // 10), replace=False)
+            rows.append(np.unique(np.concatenate([start + np.arange(band), far])))
+        rows.append(np.unique(np.concatenate([[0, n - 1], rng.choice(n, target, replace=False)])))  # wide
+    hl = _layers_from_rows(n, rows, c, 600 + c, sr)
+    M = spg.spgemm_merge_layers(plan, sr, [to_dev(L, sr) for L in hl])
+    ref = oracle.merge(hl, sr, nthreads=2)
+    got = to_host(M)
+    assert_same_structure(got, ref)
+    assert_values(got, ref, sr)
+    assert got.val.tobytes() == ref.val.tobytes()
