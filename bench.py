@@ -296,6 +296,24 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) * 1e3 / reps, r
 
 
+def _time_median(fn, reps):
+    """Median of per-call times (each call synchronized), after one warmup
+    call: for calls that wait on the GPU themselves, so one slow call (an
+    allocation, a clock change) does not move the figure."""
+    import torch
+    r = fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2], r
+
+
 def learned_modes(A2, dA2, args):
     """Single-pass product with the trained predictor against the two-phase
     product and against single-pass sizing without a predictor (capacity =
@@ -447,10 +465,10 @@ def layered_modes(args, profile=False):
     dA = spg.DeviceCSR.from_arrays(A.nrows, A.ncols, A.row_ptr, A.col, A.val)
     dB = spg.DeviceCSR.from_arrays(B.nrows, B.ncols, B.row_ptr, B.col, B.val)
     plan = spg.Plan(profile=profile)
-    t_full, C = _time(lambda: spg.spgemm(plan, "f64", dA, dB), 3)
+    t_full, C = _time_median(lambda: spg.spgemm(plan, "f64", dA, dB), 5)
     flops = plan.stats()["flops"]
     if profile:
-        unsplit_kernels = kernel_table(plan, 4)
+        unsplit_kernels = kernel_table(plan, 6)
         plan.profile_reset()
     out = {"workload": "ER (.25,.25,.25,.25) scale 18 edge factor 16, A*B FP64", "flops": flops,
            "nnz_c": C.nnz, "unsplit": {"ms": round(t_full, 4), "gflops": round(2.0 * flops / t_full / 1e6, 3)}}
@@ -464,11 +482,11 @@ def layered_modes(args, profile=False):
                 layers.append(spg.spgemm(plan, "f64", dA, dB, lo, hi))
             return layers
 
-        t_prod, _ = _time(products, 3)
+        t_prod, _ = _time_median(products, 5)
         if profile:
-            prod_kernels = kernel_table(plan, 4)
+            prod_kernels = kernel_table(plan, 6)
             plan.profile_reset()
-        t_merge, M = _time(lambda: spg.spgemm_merge_layers(plan, "f64", layers), 3)
+        t_merge, M = _time_median(lambda: spg.spgemm_merge_layers(plan, "f64", layers), 5)
         assert M.nnz == C.nnz
         # merge model: every layer read once, C written once (CSR bytes)
         w_merge = sum(8.0 * (L.nrows + 1) + 12.0 * L.nnz for L in layers) + 8.0 * (M.nrows + 1) + 12.0 * M.nnz
@@ -480,7 +498,7 @@ def layered_modes(args, profile=False):
                           "merge_model_frac": round(w_merge / t_merge / 1e6 / HBM_PEAK_GBS, 4)}
         if profile:
             out["c%d" % c]["layer_kernels"] = prod_kernels
-            out["c%d" % c]["merge_kernels"] = kernel_table(plan, 4)
+            out["c%d" % c]["merge_kernels"] = kernel_table(plan, 6)
             plan.profile_reset()
         del layers
     if profile:
