@@ -136,6 +136,82 @@ __global__ void __launch_bounds__(256) k_merge_kway(int32_t c, LayerSet layers, 
     }
 }
 
+// Count pass of the WAVE and SORT bins (rows of at most MS_LMAX entries):
+// counting needs no order, so the row's columns are inserted into an LDS
+// hash set of MC_SLOTS slots (at most half full), one wave per row, and
+// each new column counts once.  Every lane then clears the slots it
+// filled, so the set is empty again for the wave's next row.
+constexpr int MC_LOG2 = 10;
+constexpr int MC_SLOTS = 1 << MC_LOG2;
+static_assert(MC_SLOTS >= 2 * MS_LMAX && MS_LMAX >= KW_LMAX, "the hash count takes both bins' rows");
+
+__global__ void __launch_bounds__(256) k_merge_count_hash(int32_t c, LayerSet layers, BinRef ref, int64_t* cnt) {
+    constexpr int NU = MS_LMAX / SPG_WAVE;
+    __shared__ int32_t tab[4][MC_SLOTS];
+    int32_t* T = tab[threadIdx.x >> 6];
+    const int lane = lane_id();
+    for (int t = lane; t < MC_SLOTS; t += SPG_WAVE) T[t] = -1;
+    wave_lds_sync();
+    const int32_t* rows;
+    int64_t n;
+    ref.locate(rows, n);
+    int top = 1;  // search width over the layers
+    while (top < c) top <<= 1;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n; r += (int64_t)gridDim.x * 4) {
+        const int64_t i = rows[r];
+        int64_t rs = 0;
+        int32_t len = 0;
+        const int32_t* colp = nullptr;
+        if (lane < c) {
+            colp = layers.d[lane].col;
+            rs = layers.d[lane].rp[i];
+            len = (int32_t)(layers.d[lane].rp[i + 1] - rs);
+        }
+        const int32_t incl = wave_inclusive_scan_add(len);
+        const int32_t soff = incl - len;
+        const int32_t L = __builtin_amdgcn_readlane(incl, SPG_WAVE - 1);
+        int32_t mine = 0;
+        int32_t used[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) used[u] = -1;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            if (u * SPG_WAVE >= L) break;
+            const int32_t x = u * SPG_WAVE + lane;
+            int l = 0;
+            for (int step = top >> 1; step > 0; step >>= 1) {
+                const int cand = l + step;
+                const int32_t so = __shfl(soff, cand < SPG_WAVE ? cand : SPG_WAVE - 1, SPG_WAVE);
+                if (cand < c && so <= x) l = cand;
+            }
+            const int32_t lo = __shfl(soff, l, SPG_WAVE);
+            const int64_t st = __shfl((long long)rs, l, SPG_WAVE);
+            const int32_t* cp = (const int32_t*)__shfl((long long)(intptr_t)colp, l, SPG_WAVE);
+            if (x < L) {
+                const int32_t col = cp[st + (x - lo)];
+                uint32_t h = hash_slot(col, MC_LOG2);
+                while (true) {  // ends: the set is at most half full
+                    const int32_t old = atomicCAS(&T[h], -1, col);
+                    if (old == -1) {
+                        ++mine;
+                        used[u] = (int32_t)h;
+                        break;
+                    }
+                    if (old == col) break;
+                    h = (h + 1) & (MC_SLOTS - 1);
+                }
+            }
+        }
+        const int32_t tot = wave_reduce_add(mine);
+        if (lane == 0) cnt[i] = tot;
+        wave_lds_sync();  // every insertion is done before the set is cleared
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (used[u] >= 0) T[used[u]] = -1;
+        wave_lds_sync();
+    }
+}
+
 // Per-wave LDS of the bucket-sort merge: the row's keys, its values by
 // staged index (fill pass), the bucket counters.
 template <typename V, bool FILL>

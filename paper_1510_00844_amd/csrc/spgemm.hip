@@ -1308,19 +1308,16 @@ static spg_status merge_launch(spg_plan P, int32_t c, const LayerSet& ls, int64_
         const int64_t nr = counts[bb];
         if (nr == 0) continue;
         const BinRef ref{dev_counts, lists, bb};
-        if (bb == MBIN_WAVE) {
-            if (cnt) SPG_TRY((merge_kway_launch<SR, false>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
-            else SPG_TRY((merge_kway_launch<SR, true>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
+        if ((bb == MBIN_WAVE || bb == MBIN_SORT) && cnt) {
+            SPG_TRY(launch(P, "merge_count_hash", [&] {
+                k_merge_count_hash<<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt);
+            }));
+        } else if (bb == MBIN_WAVE) {
+            SPG_TRY((merge_kway_launch<SR, true>(P, c, ls, ref, nr, cnt, orp, ocol, oval)));
         } else if (bb == MBIN_SORT) {
-            if (cnt) {
-                SPG_TRY(launch(P, "merge_sort_count", [&] {
-                    k_merge_sort<SR, false><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
-                }));
-            } else {
-                SPG_TRY(launch(P, "merge_sort", [&] {
-                    k_merge_sort<SR, true><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
-                }));
-            }
+            SPG_TRY(launch(P, "merge_sort", [&] {
+                k_merge_sort<SR, true><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
+            }));
         } else if (bb == MBIN_SMALL) {
             SPG_TRY(launch(P, "merge_small", [&] {
                 k_merge_small<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(c, ls, ref, cnt, orp, ocol, oval);
