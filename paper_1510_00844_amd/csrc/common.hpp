@@ -318,6 +318,13 @@ __device__ inline uint32_t hash_slot(int32_t key, int log2t) {
     return ((uint32_t)key * 2654435761u) >> (32 - log2t);
 }
 
+// LDS writes of one lane visible to the other lanes of the wave.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sorts the n <= N keys keys[off, off + n) of the calling thread ascending,
 // in registers: unused places hold the largest key, a bitonic network of
 // compile-time comparators (a min and a max each) orders them, and the first
@@ -370,9 +377,7 @@ __device__ inline void wave_lds_bitonic_u32(uint32_t* keys, int P) {
                     keys[l] = x;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_lds_sync();
         }
     }
 }

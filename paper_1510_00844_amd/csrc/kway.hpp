@@ -31,13 +31,6 @@ struct KwLds {
     V val[FILL ? KW_LMAX : 1];
 };
 
-// LDS writes of one lane visible to the other lanes of the wave.
-__device__ inline void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Value of lane l (wave-uniform l) of a 64-bit quantity, as a scalar.
 __device__ inline int64_t readlane_i64_(int64_t v, int l) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);

@@ -784,11 +784,21 @@ static spg_status launch_sym_hash(spg_plan P, Csr A, Csr B, BinRef ref, int64_t 
     });
 }
 
+// Rows of the 128-, 256- and 512-slot bins (at most 384 products): one wave
+// per row, four rows per workgroup.
+static spg_status launch_sym_hash_wave(spg_plan P, int lg, Csr A, Csr B, BinRef ref, int64_t rows, int64_t* cnt) {
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    const int64_t* ae = P->a_end.as<int64_t>();
+    return launch(P, "sym_hash" + std::to_string(1 << lg), [&] {
+        k_sym_hash_wave<<<grid_for(std::max<int64_t>(rows, 1), 4), 256, 0, cs(P)>>>(A, B, ref, ab, ae, cnt);
+    });
+}
+
 static spg_status sym_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, BinRef ref, int64_t rows, int64_t* cnt) {
     switch (lg) {
-        case 7: return launch_sym_hash<64, 7>(P, A, B, ref, rows, cnt);
-        case 8: return launch_sym_hash<64, 8>(P, A, B, ref, rows, cnt);
-        case 9: return launch_sym_hash<64, 9>(P, A, B, ref, rows, cnt);
+        case 7:
+        case 8:
+        case 9: return launch_sym_hash_wave(P, lg, A, B, ref, rows, cnt);
         case 10: return launch_sym_hash<128, 10>(P, A, B, ref, rows, cnt);
         case 11: return launch_sym_hash<256, 11>(P, A, B, ref, rows, cnt);
         case 12: return launch_sym_hash<512, 12>(P, A, B, ref, rows, cnt);
