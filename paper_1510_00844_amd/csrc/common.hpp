@@ -127,6 +127,26 @@ __device__ inline T lane_xor(T v, int j) {
     return v;
 }
 
+// Value of lane l (per-lane l) of a 32- or 64-bit quantity (ds_bpermute).
+template <typename T>
+__device__ inline T lane_get(T v, int l) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 4) {
+        int u;
+        __builtin_memcpy(&u, &v, 4);
+        u = __builtin_amdgcn_ds_bpermute(l << 2, u);
+        __builtin_memcpy(&v, &u, 4);
+    } else {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)u);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)(u >> 32));
+        u = ((uint64_t)hi << 32) | lo;
+        __builtin_memcpy(&v, &u, 8);
+    }
+    return v;
+}
+
 // Value of lane i + 1 (DPP wave_shl:1) and of lane i - 1 (wave_shr:1).  The
 // end lanes (63, resp. 0) receive an unspecified value: callers exclude them.
 template <int CTRL, typename T>

@@ -171,35 +171,49 @@ __global__ void __launch_bounds__(NT) k_num_hash(Csr A, Csr B, const int32_t* ro
         tval[t] = S::zero();
     }
     __syncthreads();
-    for_each_product_u<NT, 4>(
-        a_beg[i], a_end[i], L,
-        [&](int64_t p, int64_t& bs, int32_t& len) {
-            int64_t k = A.col[p];
-            bs = B.rp[k];
-            len = (int32_t)(B.rp[k + 1] - bs);
-        },
-        [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
-        [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
-        [&](int t, const BEntry<V>& x) {
-            const int32_t j = x.col;
-            const V v = S::mul(s_av[t], x.val);
-            uint32_t h = hash_slot(j, LOG2T);
-            // the table has >= 4/3 slots per output of the symbolic count, so a
-            // probe ends within T steps; the cap only guards inputs that
-            // changed between the two phases
-            for (int probes = 0; probes < T; ++probes) {
-                int32_t cur = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (cur == EMPTY_KEY) {
-                    int32_t old = atomicCAS(&tkey[h], EMPTY_KEY, j);
-                    cur = old == EMPTY_KEY ? j : old;
-                }
-                if (cur == j) {
-                    S::lds_add(&tval[h], v);
-                    break;
-                }
-                h = (h + 1) & (T - 1);
+    // the table has >= 4/3 slots per output of the symbolic count, so a
+    // probe ends within T steps; the cap only guards inputs that changed
+    // between the two phases
+    auto insert = [&](int32_t j, V v) {
+        uint32_t h = hash_slot(j, LOG2T);
+        for (int probes = 0; probes < T; ++probes) {
+            int32_t cur = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cur == EMPTY_KEY) {
+                int32_t old = atomicCAS(&tkey[h], EMPTY_KEY, j);
+                cur = old == EMPTY_KEY ? j : old;
             }
-        });
+            if (cur == j) {
+                S::lds_add(&tval[h], v);
+                break;
+            }
+            h = (h + 1) & (T - 1);
+        }
+    };
+    if constexpr (NT == SPG_WAVE) {
+        // one wave: the lane search needs no block-wide enumeration
+        wave_products<4, V>(
+            a_beg[i], a_end[i],
+            [&](int64_t p, int64_t& bs, int32_t& len, V& av) {
+                const int64_t k = A.col[p];
+                bs = B.rp[k];
+                len = (int32_t)(B.rp[k + 1] - bs);
+                av = S::load(A.val, p);
+            },
+            [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
+            [&](V av, const BEntry<V>& x) { insert(x.col, S::mul(av, x.val)); });
+        __syncthreads();  // every insertion lands before the table is read
+    } else {
+        for_each_product_u<NT, 4>(
+            a_beg[i], a_end[i], L,
+            [&](int64_t p, int64_t& bs, int32_t& len) {
+                int64_t k = A.col[p];
+                bs = B.rp[k];
+                len = (int32_t)(B.rp[k + 1] - bs);
+            },
+            [&](int t, int64_t p) { s_av[t] = S::load(A.val, p); },
+            [&](int64_t q) { return BEntry<V>{B.col[q], S::load(B.val, q)}; },
+            [&](int t, const BEntry<V>& x) { insert(x.col, S::mul(s_av[t], x.val)); });
+    }
     // compaction: slots [t*PER, (t+1)*PER) -> registers
     int32_t rk[PER];
     V rv[PER];

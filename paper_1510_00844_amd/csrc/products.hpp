@@ -405,4 +405,54 @@ __device__ inline void for_each_product_gm(int64_t a_beg, int64_t a_end, Product
     else for_each_product_u<NT, 8, false>(a_beg, a_end, L, seg, pre, load, apply);
 }
 
+// The products of one row by one wave, for rows whose products are few or
+// whose B rows are short (no workgroup-wide enumeration, no barriers).  The
+// row's A entries are taken 64 at a time: seg(p, bs, len, pa) gives lane
+// p - base its B segment and a per-entry payload pa (the A value); a wave
+// scan of the lengths gives the segment offsets, and product x of the batch
+// (x = 64 (U s + u) + lane) lies in the last lane's segment starting at or
+// before x (a binary search across the lanes; empty segments share the
+// start of the next one).  Each lane issues its U gathers (load(q)) before
+// applying any (apply(pa, x)), so U loads are in flight.
+template <int U, typename PA, class Seg, class Load, class Apply>
+__device__ inline void wave_products(int64_t beg, int64_t end, Seg seg, Load load, Apply apply) {
+    typedef decltype(load((int64_t)0)) X;
+    const int lane = lane_id();
+    for (int64_t base = beg; base < end; base += SPG_WAVE) {
+        const int64_t p = base + lane;
+        int64_t bs = 0;
+        int32_t len = 0;
+        PA pa{};
+        if (p < end) seg(p, bs, len, pa);
+        const int32_t incl = wave_inclusive_scan_add(len);
+        const int32_t soff = incl - len;
+        const int32_t nb = __builtin_amdgcn_readlane(incl, SPG_WAVE - 1);
+        for (int32_t x0 = 0; x0 < nb; x0 += SPG_WAVE * U) {
+            int64_t q[U];
+            PA a[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t x = x0 + u * SPG_WAVE + lane;
+                int l = 0;
+#pragma unroll
+                for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
+                    const int32_t so = __shfl(soff, l + step, SPG_WAVE);
+                    if (so <= x) l += step;
+                }
+                q[u] = lane_get(bs, l) + (x - __shfl(soff, l, SPG_WAVE));
+                a[u] = lane_get(pa, l);
+                ok[u] = x < nb;
+            }
+            X v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) v[u] = load(q[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) apply(a[u], v[u]);
+        }
+    }
+}
+
 }  // namespace spg

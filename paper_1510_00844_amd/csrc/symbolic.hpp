@@ -216,11 +216,11 @@ __global__ void __launch_bounds__(NT) k_sym_hash(Csr A, Csr B, BinRef ref, const
 // HASH rows of at most 384 products (the 128-, 256- and 512-slot bins): one
 // wave per row, four rows per workgroup, each wave with its own set of
 // SW_SLOTS int32 keys (at most 3/8 full).  The row's A entries are taken 64
-// at a time: each lane holds one entry's B segment, a wave scan gives the
-// segment offsets, and product x of the batch (x = 64 u + lane) is found by
-// a binary search of the offsets across the lanes, its column inserted into
-// the set.  New columns are counted.  No block-wide product enumeration and
-// no barriers: the rows of these bins are short.
+// at a time (wave_products): each lane holds one entry's B segment, a wave
+// scan gives the segment offsets, and each product is placed by a binary
+// search of the offsets across the lanes, its column inserted into the set.
+// New columns are counted.  No block-wide product enumeration and no
+// barriers: the rows of these bins are short.
 constexpr int SW_LOG2 = 10;
 constexpr int SW_SLOTS = 1 << SW_LOG2;
 
@@ -237,47 +237,27 @@ __global__ void __launch_bounds__(256) k_sym_hash_wave(Csr A, Csr B, BinRef ref,
         const int64_t i = rows[r];
         for (int t = lane; t < SW_SLOTS / 4; t += SPG_WAVE) T4[t] = make_int4(EMPTY_KEY, EMPTY_KEY, EMPTY_KEY, EMPTY_KEY);
         wave_lds_sync();
-        const int64_t beg = a_beg[i], end = a_end[i];
         int32_t mine = 0;
-        for (int64_t base = beg; base < end; base += SPG_WAVE) {
-            const int64_t p = base + lane;
-            int64_t bs = 0;
-            int32_t len = 0;
-            if (p < end) {
+        wave_products<4, int32_t>(
+            a_beg[i], a_end[i],
+            [&](int64_t p, int64_t& bs, int32_t& len, int32_t&) {
                 const int64_t k = A.col[p];
                 bs = B.rp[k];
                 len = (int32_t)(B.rp[k + 1] - bs);
-            }
-            const int32_t incl = wave_inclusive_scan_add(len);
-            const int32_t soff = incl - len;
-            const int32_t nb = __builtin_amdgcn_readlane(incl, SPG_WAVE - 1);
-            for (int32_t x0 = 0; x0 < nb; x0 += SPG_WAVE) {
-                const int32_t x = x0 + lane;
-                // the last lane whose segment starts at or before x (empty
-                // segments share the start of the next one)
-                int l = 0;
-#pragma unroll
-                for (int step = SPG_WAVE / 2; step > 0; step >>= 1) {
-                    const int32_t so = __shfl(soff, l + step, SPG_WAVE);
-                    if (so <= x) l += step;
-                }
-                const int32_t lo = __shfl(soff, l, SPG_WAVE);
-                const int64_t st = __shfl((long long)bs, l, SPG_WAVE);
-                if (x < nb) {
-                    const int32_t j = B.col[st + (x - lo)];
-                    uint32_t h = hash_slot(j, SW_LOG2);
-                    while (true) {  // ends: the set is at most 3/8 full
-                        const int32_t old = atomicCAS(&T[h], EMPTY_KEY, j);
-                        if (old == EMPTY_KEY) {
-                            ++mine;
-                            break;
-                        }
-                        if (old == j) break;
-                        h = (h + 1) & (SW_SLOTS - 1);
+            },
+            [&](int64_t q) { return B.col[q]; },
+            [&](int32_t, int32_t j) {
+                uint32_t h = hash_slot(j, SW_LOG2);
+                while (true) {  // ends: the set is at most 3/8 full
+                    const int32_t old = atomicCAS(&T[h], EMPTY_KEY, j);
+                    if (old == EMPTY_KEY) {
+                        ++mine;
+                        break;
                     }
+                    if (old == j) break;
+                    h = (h + 1) & (SW_SLOTS - 1);
                 }
-            }
-        }
+            });
         const int32_t tot = wave_reduce_add(mine);
         if (lane == 0) cnt[i] = tot;
         wave_lds_sync();  // the set is read before the next row clears it
