@@ -500,7 +500,18 @@ def layered_modes(args, profile=False):
             out["c%d" % c]["layer_kernels"] = prod_kernels
             out["c%d" % c]["merge_kernels"] = kernel_table(plan, 6)
             plan.profile_reset()
-        del layers
+        del layers, M
+        # the same c layer products and their merge in one call: A's rows
+        # cut at the layer bounds (piece rows), one product, the merge as a
+        # selection product (the SUMMA stage call with one block per stage)
+        D = spg.dcsr_compress(plan, dA)
+        t_one, (Cs, snnz) = _time_median(lambda: spg.spgemm_summa_local(plan, "f64", D, dB, c, A.ncols // c), 5)
+        assert Cs.nnz == C.nnz and snnz == out["c%d" % c]["layer_nnz"]
+        out["c%d" % c]["one_call_ms"] = round(t_one, 4)
+        out["c%d" % c]["one_call_speedup"] = round((t_prod + t_merge) / t_one, 3)
+        if profile:
+            plan.profile_reset()
+        del D, Cs
     if profile:
         out["unsplit_kernels"] = unsplit_kernels
     plan.close()
