@@ -760,14 +760,15 @@ static BinParams bin_params(spg_plan P, int64_t n) {
 }
 
 // The product enumerators count a batch's products (the B-row lengths of up
-// to 1024 A entries) in int32.  With n <= 2^19 (one LDS bitmap per row) a B
-// row holds at most 2^19 entries and a batch stays below 2^29; with wider B
-// the rows that enumerate whole B rows (hash bins) are bounded by their own
-// products, so a product whose heaviest row has 2^31 or more products is
-// rejected there.
+// to 1024 A entries) in int32, and step through them up to 1024 past the
+// current one.  With n <= 2^19 (one LDS bitmap per row) a B row holds at
+// most 2^19 entries and a batch stays below 2^29; with wider B the rows that
+// enumerate whole B rows (hash bins) are bounded by their own products, so a
+// product whose heaviest row has 2^31 - 4096 or more products is rejected
+// there (the margin keeps every product index of a step inside int32).
 static spg_status check_row_products(const BinParams& bp, int64_t max_row_flops) {
-    if (!bp.dense_ok && max_row_flops >= (1ll << 31) - 1)
-        return fail(SPG_ERR_INDEX_RANGE, "a row has 2^31 or more products and B has more than 2^19 columns");
+    if (!bp.dense_ok && max_row_flops >= (1ll << 31) - 4096)
+        return fail(SPG_ERR_INDEX_RANGE, "a row has 2^31 - 4096 or more products and B has more than 2^19 columns");
     return SPG_OK;
 }
 
