@@ -480,3 +480,47 @@ def test_hash_row_orders(plan, sr):
         assert sum(st["num_rows"][3:11]) == A.nrows, "rows outside the hash bins"
         check_full_vs_oracle(C, A, B, sr)
     assert seen >= {"bitmap", "net8", "net16", "net32", "in_place", "full_sort"}, seen
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64", "bool"])
+def test_wave_enumeration_rows(plan, sr):
+    """Rows of the one-wave hash kernels whose products span several batches
+    of 64 A entries (150 and 200 A entries over short or empty B rows) and
+    rows with few outputs but thousands of products (50 B rows sharing the
+    same 300 columns: 15,000 products, 300 outputs, so the numeric pass
+    takes the 512-slot one-wave kernel), also through inner windows, all
+    against the oracle."""
+    rng = np.random.default_rng(81)
+    n = 50000
+    brows, bcols = [], []
+    k = 0
+    shared = rng.choice(n, 300, replace=False)
+    dup_rows = list(range(k, k + 50))
+    for r in dup_rows:
+        brows += [r] * 300
+        bcols += shared.tolist()
+    k += 50
+    short_rows = list(range(k, k + 600))
+    for r in short_rows:
+        c = int(rng.integers(0, 4))  # 0..3 entries, some rows empty
+        brows += [r] * c
+        bcols += rng.choice(n, c, replace=False).tolist()
+    k += 600
+    B = synth.canonical_from_coo(k, n, np.array(brows), np.array(bcols), rng.random(len(brows)) + 0.5, dup="first")
+    arows, acols = [], []
+    specs = [dup_rows, dup_rows[:20], rng.choice(short_rows, 150, replace=False).tolist(),
+             rng.choice(short_rows, 200, replace=False).tolist(), short_rows[:70],
+             rng.choice(short_rows, 100, replace=False).tolist() + dup_rows[:3]]
+    for i, ks in enumerate(specs):
+        arows += [i] * len(ks)
+        acols += [int(x) for x in ks]
+    A = synth.canonical_from_coo(len(specs), k, np.array(arows), np.array(acols), rng.random(len(arows)) + 0.5,
+                                 dup="first")
+    A, B = (A, B) if sr == "f64" else (with_kind(A, sr), with_kind(B, sr))
+    for lo, hi in ((0, k), (10, 400), (40, 650)):
+        print("case wave rows sr=%s window=(%d,%d)" % (sr, lo, hi), flush=True)
+        C = run(plan, sr, A, B, lo, hi)
+        check_full_vs_oracle(C, A, B, sr, lo, hi)
+    run(plan, sr, A, B)
+    st = plan.stats()
+    assert st["num_rows"][5] > 0, "no row in the 512-slot numeric bin"
