@@ -6,8 +6,8 @@
 // report the row's true count.  A row whose true count exceeds its capacity
 // (or which is too large for any single-pass accumulator) is recomputed by
 // the exact two-phase method; then the exact counts are scanned and the
-// slots are compacted into canonical CSR.  The exact count is the judge of
-// every prediction.
+// slots are compacted into canonical CSR.  Every prediction is checked
+// against the exact count.
 #pragma once
 #include "mlp.hpp"
 #include "numeric.hpp"
