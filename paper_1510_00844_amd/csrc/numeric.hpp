@@ -41,14 +41,21 @@ struct OutRows {
     __device__ int64_t count(int64_t i) const { return rp[i + 1] - rp[i]; }
 };
 
-// One wave per row, rows given by a list.
-template <int SR>
+// Rows of one A entry in the window: C(i,:) = a * B(k,:), a copy.  Each row
+// takes G lanes (256 / G rows per workgroup): with G = 16 a wave keeps the
+// dependent loads (row, A entry, B row extent) of four rows in flight, for
+// bins whose B rows are short (most lanes of a whole wave would idle); G =
+// 64 (a wave per row) for long B rows (R-MAT hubs), where 16 lanes would
+// need four times the steps.
+template <int SR, int G>
 __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* rows, int32_t nrows,
                                                   const int64_t* a_beg, OutRows c_rp,
                                                   int32_t* c_col, void* c_val) {
     typedef Sr<SR> S;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= nrows) return;
+    static_assert(G == 16 || G == 32 || G == 64, "lanes per row");
+    const int r = blockIdx.x * (256 / G) + (int)(threadIdx.x / G);
+    if (r >= nrows) return;  // no barriers below
+    const int g = (int)(threadIdx.x % G);
     const int64_t i = rows[r];
     const int64_t p = a_beg[i];
     const int64_t k = A.col[p];
@@ -58,13 +65,12 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
     // four strides of the row loaded before any is stored, so the loads of
     // a long B row overlap instead of waiting one stride at a time
     constexpr int U = 4;
-    const int lane = lane_id();
-    for (int64_t q0 = bs; q0 < be; q0 += U * SPG_WAVE) {
+    for (int64_t q0 = bs; q0 < be; q0 += U * G) {
         int32_t cc[U];
         typename S::acc_t vv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t q = q0 + u * SPG_WAVE + lane;
+            const int64_t q = q0 + u * G + g;
             cc[u] = 0;
             vv[u] = S::zero();
             if (q < be) {
@@ -74,7 +80,7 @@ __global__ void __launch_bounds__(256) k_num_tiny(Csr A, Csr B, const int32_t* r
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t q = q0 + u * SPG_WAVE + lane;
+            const int64_t q = q0 + u * G + g;
             if (q < be) {
                 c_col[off + q] = cc[u];
                 if (c_val) S::store(c_val, off + q, S::mul(a, vv[u]));

@@ -1164,6 +1164,23 @@ static spg_status num_hash_dispatch(spg_plan P, int lg, Csr A, Csr B, const int3
     return fail(SPG_ERR_ARG, "bad numeric hash bin");
 }
 
+// The tiny bin (one A entry per row: a scaled copy of one B row): 16 lanes
+// per row when its rows copy at most 64 entries on average, a wave per row
+// otherwise (ER-like layers: about 16 entries a row; R-MAT: hundreds).
+template <int SR>
+static spg_status launch_num_tiny(spg_plan P, Csr a, Csr b, const int32_t* rows, int64_t nr, int64_t products,
+                                  OutRows out, int32_t* col, void* val) {
+    const int64_t* ab = P->a_beg.as<int64_t>();
+    if (products <= 64 * nr) {
+        return launch(P, "num_tiny", [&] {
+            k_num_tiny<SR, 16><<<grid_for(nr, 16), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, out, col, val);
+        });
+    }
+    return launch(P, "num_tiny", [&] {
+        k_num_tiny<SR, 64><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, out, col, val);
+    });
+}
+
 // Numeric pass: every bin's kernel, launched with the counts the symbolic
 // pass read back (its preparation -- split table, work order, rank-chunk
 // items -- ran inside the symbolic pass).
@@ -1194,9 +1211,7 @@ static spg_status numeric_sr(spg_plan P, Csr a, Csr b, const int64_t* c_row_ptr,
         if (nr == 0 || bb == BIN_EMPTY) continue;
         use_stream(P, nload, (int)oi, P->num_counts, bb);
         if (bb == BIN_TINY) {
-            SPG_TRY(launch(P, "num_tiny", [&] {
-                k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, crp, ccol, cval);
-            }));
+            SPG_TRY(launch_num_tiny<SR>(P, a, b, rows, nr, P->num_counts[NBINS + BIN_TINY], crp, ccol, cval));
         } else if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "num_small", [&] {
                 k_num_small<SR><<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, crp, ccol, cval, nullptr);
@@ -1988,9 +2003,7 @@ static spg_status learned_launch(spg_plan P, Csr a, Csr b, int32_t nwords) {
         if (nr == 0 || bb == BIN_EMPTY || bb == BIN_DENSE) continue;
         use_stream(P, lload, (int)oi, P->l_counts, bb);
         if (bb == BIN_TINY) {
-            SPG_TRY(launch(P, "num_tiny", [&] {
-                k_num_tiny<SR><<<grid_for(nr, 4), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, slot, pcol, pval);
-            }));
+            SPG_TRY(launch_num_tiny<SR>(P, a, b, rows, nr, P->l_counts[NBINS + BIN_TINY], slot, pcol, pval));
         } else if (bb == BIN_SMALL) {
             SPG_TRY(launch(P, "num_small", [&] {
                 k_num_small<SR><<<grid_for(nr, 4 * SMALL_ROWS), 256, 0, cs(P)>>>(a, b, rows, (int32_t)nr, ab, ae, slot, pcol, pval,
