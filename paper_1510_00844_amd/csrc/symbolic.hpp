@@ -144,30 +144,53 @@ __device__ inline void for_small_rows(const Csr& A, const Csr& B, const int32_t*
 }
 
 // 4 waves per block, SMALL_ROWS rows per wave, the waves striding over the
-// bin's rows (located on the device).
+// bin's rows (located on the device).  A row's (at most 64) product columns
+// are counted by inserting them into a per-row LDS set of SS_SLOTS int32
+// keys (at most half full): one insertion per lane, no sort.
+constexpr int SS_LOG2 = 7;
+constexpr int SS_SLOTS = 1 << SS_LOG2;
+static_assert(SS_SLOTS >= 2 * SPG_WAVE && SS_SLOTS % SPG_WAVE == 0, "a set holds a row's products at most half full");
+
 __global__ void __launch_bounds__(256) k_sym_small(Csr A, Csr B, BinRef ref, const int64_t* a_beg,
                                                    const int64_t* a_end, int64_t* cnt) {
+    __shared__ int32_t sets[4][SMALL_ROWS][SS_SLOTS];
     const int32_t* rows;
     int64_t nrows;
     ref.locate(rows, nrows);
     const int lane = lane_id();
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * SMALL_ROWS < nrows;
-         w += (int64_t)gridDim.x * 4) {
-        uint64_t keys[SMALL_ROWS];
+    const int wv = (int)(threadIdx.x >> 6);
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wv; w * SMALL_ROWS < nrows; w += (int64_t)gridDim.x * 4) {
+#pragma unroll
+        for (int u = 0; u < SMALL_ROWS; ++u)
+            for (int t = lane; t < SS_SLOTS; t += SPG_WAVE) sets[wv][u][t] = EMPTY_KEY;
+        wave_lds_sync();
+        int32_t mine[SMALL_ROWS];
         int64_t row[SMALL_ROWS];
         for_small_rows(A, B, rows, nrows, w, a_beg, a_end, [&](int u, int64_t i, bool have, int64_t, int64_t q) {
-            keys[u] = have ? (uint64_t)(uint32_t)B.col[q] : ~0ull;
             row[u] = i;
+            mine[u] = 0;
+            if (have) {
+                const int32_t j = B.col[q];
+                int32_t* T = sets[wv][u];
+                uint32_t h = hash_slot(j, SS_LOG2);
+                while (true) {  // ends: the set is at most half full
+                    const int32_t old = atomicCAS(&T[h], EMPTY_KEY, j);
+                    if (old == EMPTY_KEY) {
+                        mine[u] = 1;
+                        break;
+                    }
+                    if (old == j) break;
+                    h = (h + 1) & (SS_SLOTS - 1);
+                }
+            }
         });
 #pragma unroll
         for (int u = 0; u < SMALL_ROWS; ++u) {
             if (w * SMALL_ROWS + u >= nrows) break;
-            const uint64_t key = wave_bitonic_sort_u64(keys[u]);
-            const uint64_t prev = lane_prev(key);
-            const bool head = key != ~0ull && (lane == 0 || prev != key);
-            const uint64_t heads = __ballot(head);
-            if (lane == 0) cnt[row[u]] = __popcll(heads);
+            const int32_t tot = wave_reduce_add(mine[u]);
+            if (lane == 0) cnt[row[u]] = tot;
         }
+        wave_lds_sync();  // the sets are read before the next rows clear them
     }
 }
 
