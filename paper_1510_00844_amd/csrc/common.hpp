@@ -334,6 +334,24 @@ __device__ inline uint64_t wave_bitonic_sort_u64(uint64_t key) {
     return key;
 }
 
+// The same sort for 32-bit keys: one lane exchange, a min and a max per
+// step instead of two exchanges and 64-bit selects.
+__device__ inline uint32_t wave_bitonic_sort_u32(uint32_t key) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= SPG_WAVE; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = lane_xor_u32(key, j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            const uint32_t mn = key < o ? key : o;
+            const uint32_t mx = key < o ? o : key;
+            key = keep_min ? mn : mx;
+        }
+    }
+    return key;
+}
+
 __device__ inline uint32_t hash_slot(int32_t key, int log2t) {
     return ((uint32_t)key * 2654435761u) >> (32 - log2t);
 }

@@ -117,7 +117,15 @@ __global__ void __launch_bounds__(256) k_num_small(Csr A, Csr B, const int32_t* 
     for (int u = 0; u < SMALL_ROWS; ++u) {
         if (w * SMALL_ROWS + u >= nrows) break;
         const int64_t i = row[u];
-        const uint64_t key = wave_bitonic_sort_u64(keys[u]);
+        // (column, lane) fits 32 bits below 2^26 - 1 columns (the all-ones
+        // key stays the empty lane's): the cheaper 32-bit sort
+        uint64_t key;
+        if (B.ncols < (1ll << 26) - 1) {
+            const uint32_t k32 = wave_bitonic_sort_u32((uint32_t)keys[u]);
+            key = k32 == 0xffffffffu ? ~0ull : (uint64_t)k32;
+        } else {
+            key = wave_bitonic_sort_u64(keys[u]);
+        }
         const bool valid = key != ~0ull;
         const V v = __shfl(vals[u], (int)(key & 63), SPG_WAVE);  // value travels with its key
         const uint64_t col = key >> 6;
