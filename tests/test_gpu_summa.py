@@ -241,3 +241,14 @@ def test_summa_rmat_s20_share(plan, share20, b):
     A, B = share20
     got, snnz = check_summa(plan, "f64", A, B, 16, b)
     assert got.nzr > 0 and snnz >= got.nnz
+
+
+@pytest.mark.parametrize("sr", ["f64", "i64"])
+@pytest.mark.parametrize("c", [4, 16])
+def test_summa_layers_in_one_call(plan, sr, c):
+    """The layered product of the C3 shape (ER A and B, the inner dimension
+    in c contiguous layers) as one stage call with one block per layer:
+    equal to the oracle's sum of the c layer products in layer order."""
+    A = synth.rmat(15, 16, synth.ER, seed=91)
+    B = synth.rmat(15, 16, synth.ER, seed=92)
+    check_summa(plan, sr, _values(sr, A), _values(sr, B), c, A.ncols // c)
